@@ -1,0 +1,191 @@
+"""ctypes front end of liblbm_oracle.so (test infrastructure).
+
+Array layout on this side: populations f[ny, nx, 9] (all rows, ghost rows unused), densities rho[ny, nx].
+Angles are in radians.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class OraParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("periodic_y", C.c_int32), ("wet_iters", C.c_int32),
+        ("tau", C.c_double), ("G", C.c_double), ("A", C.c_double),
+        ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("T", C.c_double),
+        ("body_fx", C.c_double), ("body_fy", C.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = C.CDLL(path)
+        d, i32, i64, p = C.c_double, C.c_int32, C.c_int64, C.c_void_p
+        pp = C.POINTER(OraParams)
+        L.ora_cs_pressure.argtypes = [d, d, d, d, d]; L.ora_cs_pressure.restype = d
+        L.ora_cs_dpdrho.argtypes = [d, d, d, d, d]; L.ora_cs_dpdrho.restype = d
+        L.ora_cs_d2pdrho2.argtypes = [d, d, d, d, d]; L.ora_cs_d2pdrho2.restype = d
+        L.ora_cs_mu.argtypes = [d, d, d, d, d]; L.ora_cs_mu.restype = d
+        L.ora_cs_critical.argtypes = [d, d, d, p, p, p]; L.ora_cs_critical.restype = C.c_int
+        L.ora_cs_maxwell.argtypes = [d, d, d, d, p, p]; L.ora_cs_maxwell.restype = C.c_int
+        L.ora_cs_rho_cap.argtypes = [d, d, d, d, d]; L.ora_cs_rho_cap.restype = d
+        L.ora_run.argtypes = [pp, p, i64, p, p, p]; L.ora_run.restype = C.c_int
+        L.ora_run_cplx.argtypes = [pp, p, i64, p, p, p, p]; L.ora_run_cplx.restype = C.c_int
+        L.ora_density.argtypes = [pp, p, p, p, p, p]; L.ora_density.restype = C.c_int
+        L.ora_force.argtypes = [pp, p, p, p, p, p]; L.ora_force.restype = C.c_int
+        L.ora_collide_node.argtypes = [pp, p, d, d, p]; L.ora_collide_node.restype = C.c_int
+        L.ora_ghost_density.argtypes = [d, d, d, d, d, i32]; L.ora_ghost_density.restype = d
+        L.ora_psi.argtypes = [pp, d]; L.ora_psi.restype = d
+        L.ora_init_droplets.argtypes = [pp, p, i32, p, p, p, d, d, d]; L.ora_init_droplets.restype = C.c_int
+        L.ora_mass.argtypes = [pp, p]; L.ora_mass.restype = d
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------------------------------------------ EOS helpers
+def cs_pressure(rho, T, a=1.0, b=4.0, R=1.0):
+    return lib().ora_cs_pressure(a, b, R, T, float(rho))
+
+
+def cs_dpdrho(rho, T, a=1.0, b=4.0, R=1.0):
+    return lib().ora_cs_dpdrho(a, b, R, T, float(rho))
+
+
+def cs_d2pdrho2(rho, T, a=1.0, b=4.0, R=1.0):
+    return lib().ora_cs_d2pdrho2(a, b, R, T, float(rho))
+
+
+def cs_mu(rho, T, a=1.0, b=4.0, R=1.0):
+    return lib().ora_cs_mu(a, b, R, T, float(rho))
+
+
+def cs_critical(a=1.0, b=4.0, R=1.0):
+    """(rho_c, T_c, p_c) of the Carnahan-Starling EOS."""
+    rc, tc, pc = C.c_double(), C.c_double(), C.c_double()
+    rc_ = lib().ora_cs_critical(a, b, R, C.byref(rc), C.byref(tc), C.byref(pc))
+    if rc_:
+        raise ValueError("critical point: no root")
+    return rc.value, tc.value, pc.value
+
+
+def cs_maxwell(T, a=1.0, b=4.0, R=1.0):
+    """Maxwell coexistence densities (rho_v, rho_l) at absolute temperature T."""
+    rv, rl = C.c_double(), C.c_double()
+    rc_ = lib().ora_cs_maxwell(a, b, R, T, C.byref(rv), C.byref(rl))
+    if rc_:
+        raise ValueError(f"maxwell: failed ({rc_})")
+    return rv.value, rl.value
+
+
+def cs_rho_cap(T, G=-1.0, a=1.0, b=4.0, R=1.0):
+    return lib().ora_cs_rho_cap(a, b, R, T, G)
+
+
+def ghost_density(r_im1_1, r_ip1_1, r_i_1, r_i_2, theta, iters):
+    return lib().ora_ghost_density(float(r_im1_1), float(r_ip1_1), float(r_i_1), float(r_i_2), float(theta),
+                                   int(iters))
+
+
+# ------------------------------------------------------------------------------------------------ simulation
+class Sim:
+    """One lattice (state in self.f, [ny, nx, 9] float64) advanced by the reference step."""
+
+    def __init__(self, nx, ny, T_over_Tc, theta_bottom=np.pi / 2, theta_top=np.pi / 2, *, wet_iters=4, tau=1.0,
+                 G=-1.0, A=-0.6, a=1.0, b=4.0, R=1.0, body_force=(0.0, 0.0), periodic_y=False):
+        rc, tc, pc = cs_critical(a, b, R)
+        self.T_c = tc
+        self.T = T_over_Tc * tc
+        self.p = OraParams(nx, ny, 1 if periodic_y else 0, wet_iters, tau, G, A, a, b, R, self.T,
+                           body_force[0], body_force[1])
+        self.nx, self.ny = nx, ny
+        self.f = np.zeros((ny, nx, 9), dtype=np.float64)
+        self.theta_b = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_bottom, np.float64), (nx,)))
+        self.theta_t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_top, np.float64), (nx,)))
+        self.counters = np.zeros(2, dtype=np.int64)
+        self.steps = 0
+
+    def coexistence(self):
+        return cs_maxwell(self.T, self.p.eos_a, self.p.eos_b, self.p.eos_R)
+
+    def init_droplets(self, xc, yc, R, width=5.0, rho_l=None, rho_v=None):
+        xc = np.ascontiguousarray(np.atleast_1d(np.asarray(xc, np.float64)))
+        yc = np.ascontiguousarray(np.atleast_1d(np.asarray(yc, np.float64)))
+        R = np.ascontiguousarray(np.atleast_1d(np.asarray(R, np.float64)))
+        if rho_l is None or rho_v is None:
+            rv, rl = self.coexistence()
+            rho_l = rl if rho_l is None else rho_l
+            rho_v = rv if rho_v is None else rho_v
+        rc_ = lib().ora_init_droplets(C.byref(self.p), _ptr(self.f), len(xc), _ptr(xc), _ptr(yc), _ptr(R),
+                                      float(width), float(rho_l), float(rho_v))
+        if rc_:
+            raise ValueError("init_droplets failed")
+        self.steps = 0
+
+    def run(self, nsteps):
+        rc_ = lib().ora_run(C.byref(self.p), _ptr(self.f), int(nsteps), _ptr(self.theta_b), _ptr(self.theta_t),
+                            _ptr(self.counters))
+        if rc_:
+            raise ValueError("run failed")
+        self.steps += nsteps
+
+    def density(self):
+        """(rho, psi), [ny, nx] each; ghost rows hold the wetting densities of the current state."""
+        rho = np.zeros((self.ny, self.nx))
+        psi = np.zeros((self.ny, self.nx))
+        rc_ = lib().ora_density(C.byref(self.p), _ptr(self.f), _ptr(self.theta_b), _ptr(self.theta_t), _ptr(rho),
+                                _ptr(psi))
+        if rc_:
+            raise ValueError("density failed")
+        return rho, psi
+
+    def force(self):
+        Fx = np.zeros((self.ny, self.nx))
+        Fy = np.zeros((self.ny, self.nx))
+        lib().ora_force(C.byref(self.p), _ptr(self.f), _ptr(self.theta_b), _ptr(self.theta_t), _ptr(Fx), _ptr(Fy))
+        return Fx, Fy
+
+    def mass(self):
+        return lib().ora_mass(C.byref(self.p), _ptr(self.f))
+
+    def fluid_rows(self):
+        return slice(0, self.ny) if self.p.periodic_y else slice(1, self.ny - 1)
+
+    def run_cplx(self, nsteps, f, theta_b, theta_t, G_f, G_psi):
+        """Complex-step run from complex inputs; returns the complex populations."""
+        fc = np.ascontiguousarray(f, dtype=np.complex128).copy()
+        tb = np.ascontiguousarray(np.broadcast_to(theta_b, (self.nx,)), dtype=np.complex128)
+        tt = np.ascontiguousarray(np.broadcast_to(theta_t, (self.nx,)), dtype=np.complex128)
+        gf = np.array([complex(G_f)], dtype=np.complex128)
+        gp = np.array([complex(G_psi)], dtype=np.complex128)
+        rc_ = lib().ora_run_cplx(C.byref(self.p), _ptr(fc), int(nsteps), _ptr(tb), _ptr(tt), _ptr(gf), _ptr(gp))
+        if rc_:
+            raise ValueError("run_cplx failed")
+        return fc
+
+
+def collide_node(sim, f_in, Fx, Fy):
+    f_in = np.ascontiguousarray(f_in, np.float64)
+    out = np.zeros(9)
+    lib().ora_collide_node(C.byref(sim.p), _ptr(f_in), float(Fx), float(Fy), _ptr(out))
+    return out
+
+
+def psi(sim, rho):
+    return lib().ora_psi(C.byref(sim.p), float(rho))
+
+
+__all__ = ["OraParams", "lib", "cs_pressure", "cs_dpdrho", "cs_d2pdrho2", "cs_mu", "cs_critical", "cs_maxwell",
+           "cs_rho_cap", "ghost_density", "Sim", "collide_node", "psi"]
