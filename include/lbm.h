@@ -1,0 +1,178 @@
+/* liblbm — EOS-based single-component pseudo-potential lattice Boltzmann method with the geometric
+ * contact-angle wall, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hu, Li & Uddin, "Contact Angle Adjustment in Equation of States Based Pseudo-Potential Model",
+ * arXiv:1501.05430. One time step is
+ *   streamed populations f -> density rho, momentum j            (Sec. 2, Eq. 1)
+ *   -> effective density psi(rho), Carnahan-Starling EOS          (Eq. 10, c = 1)
+ *   -> ghost-layer density at each wall from theta                (Sec. 4, Eq. 19-21)
+ *   -> interaction force, hybrid form with parameter A            (Eq. 9, weights of Eq. 7)
+ *   -> BGK collision with Guo forcing, v = (j + F/2)/rho          (Eq. 1-6 with diag(0,1,...,1), Sec. 3.1)
+ *   -> streaming with halfway bounce-back at the walls.
+ *
+ * Lattice: D2Q9, velocities e0=(0,0), e1..e4=(1,0),(0,1),(-1,0),(0,-1), e5..e8=(1,1),(-1,1),(-1,-1),(1,-1)
+ * (the moment order of Eq. 4). Grid nx x ny with x periodic; rows 0 and ny-1 are the ghost layer beside the
+ * walls (Sec. 4 index 0) and carry only density and psi; rows 1..ny-2 are fluid. The wall planes sit at
+ * y = 0.5 and y = ny - 1.5.
+ *
+ * Conventions for every entry point:
+ *  - The return value is a status (lbm_status); 0 = LBM_OK. No C++ exception or abort crosses this boundary.
+ *    On failure lbm_last_error() returns a thread-local message.
+ *  - Device memory is owned by the caller: one workspace of lbm_workspace_bytes() bytes, passed to lbm_create.
+ *    The library never allocates or frees device memory. lbm_destroy frees only host memory.
+ *  - Work is queued asynchronously on the HIP stream given to lbm_create, except where a function says it
+ *    synchronizes that stream. A context is not thread-safe; use one context per stream.
+ *  - Pointers named d_* are device pointers; all others are host pointers. Angles are in radians.
+ *  - Invalid arguments return LBM_E_INVALID before any work is queued.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_API_VERSION 1
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = 1,     /* bad argument or parameter */
+  LBM_E_WORKSPACE = 2,   /* workspace too small or misaligned (256 B) */
+  LBM_E_HIP = 3,         /* a HIP runtime call failed; message has the HIP error text */
+  LBM_E_UNSTABLE = 4,    /* a non-finite density was seen by a periodic check; state stays readable */
+  LBM_E_STATE = 5,       /* call out of order (e.g. stepping before lbm_init_droplet / lbm_set_populations) */
+  LBM_E_UNSUPPORTED = 6  /* valid request this build does not provide */
+} lbm_status;
+
+typedef enum {
+  LBM_F64 = 0,         /* populations stored and computed in FP64 */
+  LBM_F32 = 1,         /* populations stored and computed in FP32 */
+  LBM_F32_SHIFTED = 2  /* FP32 storage of f_i - w_i rho0 (rho0 = rho0_shift), computed in FP32 */
+} lbm_precision;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; holds host memory only */
+
+/* Parameters of one lattice instance. Defaults in brackets are the paper's / the workloads' values. */
+typedef struct {
+  int32_t nx, ny;         /* columns (periodic) and rows including both ghost rows; nx >= 2, ny >= 4 */
+  int32_t precision;      /* lbm_precision; every instance of a context must use the same one */
+  int32_t wet_iters;      /* 0: Eq. 19; k >= 1: k-th iterate of Eq. 21 (first line = iterate 1) [4] */
+  int32_t check_every;    /* steps between device checks of mass, non-finite density and clamps; 0 = none */
+  int32_t strip_rows;     /* rows per wavefront strip of the step kernel; 0 = library default */
+  int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step */
+  int32_t step_variant;   /* step kernel shape: k = 1..4 selects 1, 2, 4 or 8 wavefronts (64, 128, 256 or 512
+                             aligned columns) per block; 0 = library default. Instance 0's value applies to the
+                             whole context (lbm_autotune may change it). Results do not depend on it (bitwise). */
+  double tau;             /* BGK relaxation time (> 0.5) [1.0] */
+  double G;               /* interaction strength, < 0 [-1.0] */
+  double A;               /* hybrid-force parameter of Eq. 9 [-0.6]; 0 = plain Shan-Chen force (Eq. 7) */
+  double eos_a, eos_b, eos_R; /* Carnahan-Starling constants [1, 4, 1] */
+  double T_over_Tc;       /* temperature as a fraction of the EOS critical temperature, in (0, 1) */
+  double rho0_shift;      /* LBM_F32_SHIFTED: reference density rho0 of the stored f_i - w_i rho0 */
+  double rho_fp64_below;  /* FP32 modes: the EOS / psi is evaluated in FP64 where rho < this; 0 = never */
+  double body_force[2];   /* constant body force per unit volume (F_g of Eq. 7) [0, 0] */
+} lbm_params;
+
+/* Device diagnostics of one instance, accumulated by the periodic checks (check_every) of lbm_step. */
+typedef struct {
+  double mass;            /* FP64 sum of the populations over fluid nodes at the last check */
+  int64_t checks;         /* number of checks run since lbm_create / lbm_init_droplet */
+  int64_t nonfinite;      /* fluid nodes with a non-finite density, summed over checks */
+  int64_t psi_clamps;     /* fluid nodes where p_EOS - rho/3 had the wrong sign (psi set to 0), summed */
+  int64_t ghost_clamps;   /* ghost densities clamped into [0, rho_cap), summed over checks */
+  int64_t steps;          /* time steps taken since the last initialization */
+} lbm_diag;
+
+/* Bytes of device workspace for n_inst instances described by p[0..n_inst-1]; 0 if the parameters are
+ * invalid (lbm_last_error says why). */
+size_t lbm_workspace_bytes(const lbm_params* p, int32_t n_inst);
+
+/* Create a context over n_inst instances. d_workspace: caller-owned device memory, 256-byte aligned, at least
+ * lbm_workspace_bytes(p, n_inst) bytes, kept alive until lbm_destroy. hip_stream: a hipStream_t (NULL = the
+ * null stream; graph replay of lbm_step then falls back to plain launches). The EOS critical point, Maxwell
+ * coexistence densities and the largest density with real psi are solved on the host in FP64 here. The
+ * populations start undefined: call lbm_init_droplet or lbm_set_populations before lbm_step. */
+int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws_bytes, void* hip_stream,
+               lbm_ctx** out);
+
+int lbm_destroy(lbm_ctx* c);
+
+/* Host FP64 EOS data of instance inst: out[0] = rho_v, out[1] = rho_l (Maxwell equal-area coexistence of the
+ * Carnahan-Starling EOS), out[2] = T (absolute), out[3] = T_c, out[4] = rho_c, out[5] = rho_cap (largest
+ * density with real psi, Eq. 10). */
+int lbm_eos_info(const lbm_ctx* c, int32_t inst, double out[6]);
+
+/* Initial state (droplets at rest): rho(x, y) = rho_v + (rho_l - rho_v) (1 - tanh(2 (r - R_k)/width)) / 2,
+ * the maximum over the n droplets, r the distance from node (x, y) to (xc[k], yc[k]) with the nearest periodic
+ * image in x; f_i = w_i rho. rho_l <= 0 or rho_v <= 0 selects the Maxwell value. The setup of Sec. 3.1 is one
+ * semicircle on the bottom wall: yc = 0.5. Resets the step counter and diagnostics. Host arrays [n]. */
+int lbm_init_droplet(lbm_ctx* c, int32_t inst, int32_t n, const double* xc, const double* yc, const double* R,
+                     double width, double rho_l, double rho_v);
+
+/* Set the wall contact angles (Sec. 4): theta_bottom / theta_top are host arrays of nx angles in (0, pi),
+ * one per wall column; NULL keeps the current values (initially pi/2). Then recomputes the ghost-row densities
+ * of the current state (Eq. 19 or Eq. 21) into the context, readable with lbm_get_rho. The ghost rows are also
+ * recomputed inside every lbm_step. Synchronizes the stream (the host arrays may be reused on return). */
+int lbm_apply_wetting(lbm_ctx* c, int32_t inst, const double* theta_bottom, const double* theta_top);
+
+/* Advance nsteps time steps. inst >= 0 steps one instance; inst = -1 steps every instance with one kernel launch
+ * per step. Steps are replayed from a captured HIP graph in chunks when the stream is not the null stream.
+ * With check_every > 0 a device check runs every check_every steps and after the last step; the call then
+ * synchronizes the stream once at its end and returns LBM_E_UNSTABLE if a check saw a non-finite density. */
+int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps);
+
+/* Contact angle of the droplet inside box = {x_lo, x_hi, y_lo, y_hi} (half-open node ranges; rows are clipped
+ * to the fluid rows) on wall 0 (bottom) or 1 (top). Reading of the method (the paper quotes angles without the
+ * procedure): rho_mid = (max + min)/2 over the box; rho_mid crossings on horizontal and vertical links by linear
+ * interpolation; points within 3 nodes of the wall plane dropped; algebraic (Kasa) circle fit from FP64 moments;
+ * theta = acos((y_w - y_c)/R) (bottom) or acos((y_c - y_w)/R) (top). out = {theta, R, x_c, y_c, n_points}.
+ * Synchronizes the stream. */
+int lbm_measure_contact_angle(lbm_ctx* c, int32_t inst, int32_t wall, const int32_t box[4], double out[5]);
+
+/* FP64 total mass (sum of all populations over fluid nodes) of the current state. Synchronizes the stream. */
+int lbm_mass(lbm_ctx* c, int32_t inst, double* out);
+
+/* Diagnostics accumulated by the periodic checks. Synchronizes the stream. */
+int lbm_get_diag(lbm_ctx* c, int32_t inst, lbm_diag* out);
+
+/* Density of the current state as FP64 [ny][nx]: fluid rows sum the populations (FP64 sum of the stored values
+ * plus 9 w_i rho0 when shifted); rows 0 and ny-1 hold the ghost densities the next step will use (clamped).
+ * dst_on_device != 0: dst is a device pointer (stream-ordered); otherwise host (synchronizes). */
+int lbm_get_rho(lbm_ctx* c, int32_t inst, double* dst, int32_t dst_on_device);
+
+/* Populations of the current state as FP64 [9][ny-2][nx] (unshifted f_i, fluid rows 1..ny-2), to a device or
+ * host buffer; and the reverse (rounded to the storage precision). */
+int lbm_get_populations(lbm_ctx* c, int32_t inst, double* dst, int32_t dst_on_device);
+int lbm_set_populations(lbm_ctx* c, int32_t inst, const double* src, int32_t src_on_device);
+
+/* Raw state (the stored populations, lbm_state_bytes bytes) for checkpoint / resume, device to device. */
+size_t lbm_state_bytes(const lbm_ctx* c, int32_t inst);
+int lbm_get_state(lbm_ctx* c, int32_t inst, void* d_dst);
+int lbm_set_state(lbm_ctx* c, int32_t inst, const void* d_src);
+
+/* Choose strip_rows for the step kernel by timing trial launches of each candidate on the current state (the
+ * state is not modified: trials read the current buffer and write the spare one). trial_steps > 0 launches per
+ * candidate. inst = -1 tunes the batched launch. *chosen receives the rows per strip. Synchronizes. */
+int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen);
+
+/* Adjoint of one time step (the reverse of streaming, collision, force, wetting and psi, in that order).
+ * Given the FP64 populations f_n of step n (d_state_n, [9][ny-2][nx], unshifted) and the adjoint
+ * lambda_{n+1} = dL/df_{n+1} (same layout), writes lambda_n = (d f_{n+1} / d f_n)^T lambda_{n+1} to d_lambda_n
+ * and ACCUMULATES d_theta_bar[2][nx] += (d f_{n+1}/d theta)^T lambda_{n+1} (bottom row then top row) and
+ * d_G_bar[2] += {dL/dG_f, dL/dG_psi}, G_f being the force prefactor of Eq. 9 and G_psi the G inside Eq. 10
+ * (equal in the forward model). Needs enable_adjoint = 1 and LBM_F64; runs on the context's stream. Sub-gradient
+ * 0 at exact kinks (|T| of Eq. 19, the square root at 0, the clamps). Does not change the context's state. */
+int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const double* d_lambda_np1,
+                     double* d_lambda_n, double* d_theta_bar, double* d_G_bar);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,928 @@
+// C-ABI of liblbm (include/lbm.h): context, workspace carving, host EOS solves, stepping with HIP graph replay,
+// diagnostics and contact-angle measurement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(LBM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------------ host EOS (FP64)
+// Carnahan-Starling: p = rho R T (1 + eta + eta^2 - eta^3)/(1 - eta)^3 - a rho^2, eta = b rho/4.
+struct Eos {
+  double a, b, R, T;
+  double p(double rho) const {
+    const double e = 0.25 * b * rho, om = 1.0 - e;
+    return rho * R * T * (1.0 + e * (1.0 + e * (1.0 - e))) / (om * om * om) - a * rho * rho;
+  }
+  // dp/drho = R T Phi'(eta) - 2 a rho with Phi = eta Z, Phi' = (1 + 4e + 4e^2 - 4e^3 + e^4)/(1 - e)^4
+  double dp(double rho) const {
+    const double e = 0.25 * b * rho, om = 1.0 - e;
+    const double om2 = om * om;
+    return R * T * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om2 * om2) - 2.0 * a * rho;
+  }
+  double d2p(double rho) const {
+    const double e = 0.25 * b * rho, om = 1.0 - e;
+    const double om2 = om * om;
+    return R * T * 0.25 * b * (8.0 + e * (20.0 - 4.0 * e)) / (om2 * om2 * om) - 2.0 * a;
+  }
+  // chemical potential with mu' = p'/rho: R T [ln rho + (8e - 9e^2 + 3e^3)/(1-e)^3] - 2 a rho
+  double mu(double rho) const {
+    const double e = 0.25 * b * rho, om = 1.0 - e;
+    return R * T * (std::log(rho) + e * (8.0 + e * (-9.0 + 3.0 * e)) / (om * om * om)) - 2.0 * a * rho;
+  }
+};
+
+// Newton iteration safeguarded by bisection on a bracket [lo, hi] with f(lo), f(hi) of opposite sign.
+double safe_root(const std::function<double(double)>& f, const std::function<double(double)>& df, double lo,
+                 double hi) {
+  double flo = f(lo);
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 400; ++it) {
+    const double fx = f(x);
+    if (fx == 0.0) return x;
+    if ((fx < 0) == (flo < 0)) { lo = x; flo = fx; } else { hi = x; }
+    const double d = df(x);
+    double xn = (d != 0.0 && std::isfinite(d)) ? x - fx / d : 0.5 * (lo + hi);
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    if (std::fabs(xn - x) <= 4e-16 * std::fabs(x) || hi - lo <= 4e-16 * std::fabs(hi)) return xn;
+    x = xn;
+  }
+  return x;
+}
+
+// Critical point from the quintic 1 - 5e - 20e^2 - 4e^3 + 5e^4 - e^5 = 0 (p' = p'' = 0 with T eliminated),
+// then T_c = 8 a e_c / (b R Phi'(e_c)).
+void cs_critical(double a, double b, double R, double* rho_c, double* T_c) {
+  auto q = [](double e) { return 1.0 + e * (-5.0 + e * (-20.0 + e * (-4.0 + e * (5.0 - e)))); };
+  auto dq = [](double e) { return -5.0 + e * (-40.0 + e * (-12.0 + e * (20.0 - 5.0 * e))); };
+  const double e = safe_root(q, dq, 0.05, 0.3);
+  const double om = 1.0 - e;
+  const double phi1 = (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om * om * om * om);
+  *rho_c = 4.0 * e / b;
+  *T_c = 8.0 * a * e / (b * R * phi1);
+}
+
+// Maxwell construction: for a pressure level P the outer branches give rho_v(P) < s1 and rho_l(P) > s2; the
+// coexistence level zeroes mu(rho_l) - mu(rho_v). Regula falsi (Illinois) on P.
+bool cs_maxwell(const Eos& E, double rho_c, double* rv, double* rl) {
+  const double top = 0.9999 * 4.0 / E.b;
+  auto dp = [&](double r) { return E.dp(r); };
+  auto d2p = [&](double r) { return E.d2p(r); };
+  if (!(E.dp(rho_c) < 0)) return false;
+  const double s1 = safe_root(dp, d2p, 1e-12 * rho_c, rho_c);
+  const double s2 = safe_root(dp, d2p, rho_c, top);
+  auto branch = [&](double P, double lo, double hi) {
+    return safe_root([&](double r) { return E.p(r) - P; }, dp, lo, hi);
+  };
+  auto g = [&](double P, double* v, double* l) {
+    *v = branch(P, 1e-300, s1);
+    *l = branch(P, s2, top);
+    return E.mu(*l) - E.mu(*v);
+  };
+  double Pa = std::max(E.p(s2), 0.0) + 1e-300, Pb = E.p(s1);
+  double v, l;
+  double ga = g(Pa, &v, &l), gb = g(Pb, &v, &l);
+  if (!((ga > 0) && (gb < 0))) {
+    // mu_l - mu_v is positive at the lowest level and negative at the vapour spinodal; fall back to bisection
+    // in log P if the bracket is degenerate at the low end.
+    if (!(gb < 0)) return false;
+  }
+  int side = 0;
+  double P = Pb;
+  for (int it = 0; it < 300; ++it) {
+    P = (Pa * gb - Pb * ga) / (gb - ga);
+    if (!(P > Pa && P < Pb)) P = 0.5 * (Pa + Pb);
+    const double gp = g(P, &v, &l);
+    if (gp == 0.0 || (Pb - Pa) <= 1e-16 * Pb) break;
+    if ((gp > 0) == (ga > 0)) {
+      Pa = P; ga = gp;
+      if (side == -1) gb *= 0.5;
+      side = -1;
+    } else {
+      Pb = P; gb = gp;
+      if (side == 1) ga *= 0.5;
+      side = 1;
+    }
+  }
+  g(P, &v, &l);
+  *rv = v;
+  *rl = l;
+  return v > 0 && l > v;
+}
+
+// Largest density with real psi (Eq. 10, G < 0): the root of p(rho) - rho/3 above the liquid branch.
+double cs_rho_cap(const Eos& E, double rho_c) {
+  const double top = 0.9999 * 4.0 / E.b;
+  double lo = rho_c;
+  if (E.dp(rho_c) < 0) lo = safe_root([&](double r) { return E.dp(r); }, [&](double r) { return E.d2p(r); }, rho_c,
+                                      top);
+  auto h = [&](double r) { return E.p(r) - r / 3.0; };
+  if (!(h(lo) < 0)) return lo;
+  return safe_root(h, [&](double r) { return E.dp(r) - 1.0 / 3.0; }, lo, top);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Measured defaults on MI355X for the 4096 x 2048 lattice (autotuning can refine them per context):
+// FP32 8 wavefronts per block with prefetch and 32-row strips; FP64 4 wavefronts, no prefetch, 64-row strips.
+constexpr int kDefaultStripRows = 32;
+constexpr int kDefaultWaves = 8;
+constexpr bool kDefaultPrefetch = true;
+constexpr int kDefaultStripRows64 = 64;
+constexpr int kDefaultWaves64 = 4;
+constexpr bool kDefaultPrefetch64 = false;
+constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr int kMaxDrops = 4096;
+
+struct Inst {
+  lbm_params p;
+  int pitch = 0;
+  int64_t plane = 0;
+  double rho_c = 0, T_c = 0, T = 0, rho_v = 0, rho_l = 0, rho_cap = 0;
+  int strip_rows = kDefaultStripRows;
+  bool initialized = false;
+  int64_t steps = 0;
+  size_t off_f[2] = {0, 0}, off_th = 0, off_ghost = 0, off_adj = 0;
+  std::vector<double> cos_th, cot_th, sin_th;
+};
+
+struct Layout {
+  size_t desc, tasks, wdiag, first, idiag, drops, rho_scratch, partials, total;
+  size_t task_cap;
+  std::vector<size_t> inst_f[2], inst_th, inst_ghost, inst_adj;
+};
+
+size_t storage_bytes(int precision) { return precision == LBM_F64 ? 8 : 4; }
+
+// column blocks of 64 * waves columns (at most; see build_tasks)
+int blocks_x(int nx, int waves) { return (nx + 64 * waves - 1) / (64 * waves); }
+
+size_t adj_bytes(const lbm_params& p) {
+  const size_t pitch = (size_t)((p.nx + 63) / 64 * 64);
+  const size_t field = align256(sizeof(double) * pitch * p.ny);
+  return 4 * field + align256(sizeof(double) * 2 * p.nx) + align256(sizeof(double) * 4 * 4096);
+}
+
+bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
+  if (!p || n < 1) { *why = "need at least one instance"; return false; }
+  for (int i = 0; i < n; ++i) {
+    const lbm_params& q = p[i];
+    char b[256];
+    auto bad = [&](const char* what) {
+      snprintf(b, sizeof b, "instance %d: %s", i, what);
+      *why = b;
+      return false;
+    };
+    if (q.nx < 2 || q.ny < 4) return bad("need nx >= 2 and ny >= 4");
+    if ((int64_t)q.nx * q.ny > (int64_t)1 << 34) return bad("lattice too large");
+    if (q.ny - 2 > 65535) return bad("ny too large");
+    if (q.precision < LBM_F64 || q.precision > LBM_F32_SHIFTED) return bad("unknown precision");
+    if (q.precision != p[0].precision) return bad("all instances must share one precision");
+    if (q.wet_iters < 0 || q.wet_iters > 1000) return bad("wet_iters out of range [0, 1000]");
+    if (q.check_every < 0) return bad("check_every < 0");
+    if (q.strip_rows < 0) return bad("strip_rows < 0");
+    if (q.step_variant < 0 || q.step_variant > 2 * kNumWaveChoices) return bad("step_variant outside [0, 8]");
+    if ((int64_t)((q.nx + 63) / 64 * 64) * (q.ny - 2) * 9 >= ((int64_t)1 << 31)) return bad("lattice too large for 32-bit offsets");
+    if (!(q.tau > 0.5) || !std::isfinite(q.tau)) return bad("tau must be > 0.5");
+    if (!(q.G < 0) || !std::isfinite(q.G)) return bad("G must be negative");
+    if (!std::isfinite(q.A)) return bad("A not finite");
+    if (!(q.eos_a > 0) || !(q.eos_b > 0) || !(q.eos_R > 0)) return bad("EOS constants must be positive");
+    if (!(q.T_over_Tc > 0 && q.T_over_Tc < 1)) return bad("T_over_Tc must be in (0, 1)");
+    if (!std::isfinite(q.rho0_shift) || q.rho0_shift < 0) return bad("rho0_shift must be >= 0");
+    if (q.precision != LBM_F32_SHIFTED && q.rho0_shift != 0) return bad("rho0_shift needs LBM_F32_SHIFTED");
+    if (!std::isfinite(q.rho_fp64_below)) return bad("rho_fp64_below not finite");
+    if (!std::isfinite(q.body_force[0]) || !std::isfinite(q.body_force[1])) return bad("body force not finite");
+    if (q.enable_adjoint && q.precision != LBM_F64) return bad("the adjoint needs LBM_F64");
+  }
+  return true;
+}
+
+Layout make_layout(const lbm_params* p, int32_t n) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  L.task_cap = 0;
+  size_t max_nodes = 0;
+  for (int i = 0; i < n; ++i) {
+    L.task_cap += (size_t)blocks_x(p[i].nx, 1) * (size_t)(p[i].ny - 2);
+    max_nodes = std::max(max_nodes, (size_t)p[i].nx * p[i].ny);
+  }
+  L.desc = take(sizeof(InstDesc) * n);
+  L.tasks = take(sizeof(WaveTask) * L.task_cap);
+  L.wdiag = take(sizeof(WaveDiag) * L.task_cap);
+  L.first = take(sizeof(int32_t) * (n + 1));
+  L.idiag = take(sizeof(InstDiag) * n);
+  L.drops = take(sizeof(double) * 3 * kMaxDrops);
+  L.rho_scratch = take(sizeof(double) * max_nodes);
+  L.partials = take(sizeof(double) * kMeasureBlocks * 16);
+  for (int i = 0; i < n; ++i) {
+    const size_t pitch = (size_t)((p[i].nx + 63) / 64 * 64);
+    const size_t fbytes = storage_bytes(p[i].precision) * 9 * pitch * (size_t)(p[i].ny - 2);
+    L.inst_f[0].push_back(take(fbytes));
+    L.inst_f[1].push_back(take(fbytes));
+    L.inst_th.push_back(take(sizeof(double) * 6 * p[i].nx));
+    L.inst_ghost.push_back(take(sizeof(double) * 2 * p[i].nx));
+    L.inst_adj.push_back(p[i].enable_adjoint ? take(adj_bytes(p[i])) : 0);
+  }
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  std::vector<Inst> inst;
+  Layout L;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  int storage = STORE_F64;
+  int waves = kDefaultWaves;       // wavefronts per block of the step kernel (context-wide)
+  bool prefetch = kDefaultPrefetch;  // next row's populations in flight during the collision
+  std::vector<InstDesc> hdesc;
+  std::vector<int32_t> first;       // [n+1] task ranges per instance
+  std::vector<WaveTask> tasks;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (selection, length) -> executable graph
+
+  InstDesc* d_desc() { return (InstDesc*)(ws + L.desc); }
+  WaveTask* d_tasks() { return (WaveTask*)(ws + L.tasks); }
+  WaveDiag* d_wdiag() { return (WaveDiag*)(ws + L.wdiag); }
+  int32_t* d_first() { return (int32_t*)(ws + L.first); }
+  InstDiag* d_idiag() { return (InstDiag*)(ws + L.idiag); }
+  double* d_partials() { return (double*)(ws + L.partials); }
+  double* d_rho_scratch() { return (double*)(ws + L.rho_scratch); }
+  int n() const { return (int)inst.size(); }
+
+  // the tau = 1 collision applies when every selected instance has tau == 1 exactly
+  bool tau1(int sel) const {
+    for (int i = 0; i < n(); ++i)
+      if ((sel < 0 || i == sel) && inst[i].p.tau != 1.0) return false;
+    return true;
+  }
+
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+
+  // Block decomposition of every instance: columns in aligned runs of 64 * waves (the last run takes the rest;
+  // a 1-column remainder is merged so every block is at least 2 columns wide), rows balanced over
+  // ceil((ny-2)/strip_rows) bands. Row bands outer, column blocks inner: blocks that run at the same time cover
+  // whole contiguous rows of every population plane. Tasks of one instance are contiguous.
+  void build_tasks() {
+    tasks.clear();
+    first.assign(n() + 1, 0);
+    const int bwmax = 64 * waves;
+    for (int i = 0; i < n(); ++i) {
+      first[i] = (int)tasks.size();
+      const int nx = inst[i].p.nx, nyf = inst[i].p.ny - 2;
+      std::vector<int> xs;  // block start columns, then nx
+      for (int x = 0; x < nx; x += bwmax) xs.push_back(x);
+      xs.push_back(nx);
+      const int nb = (int)xs.size() - 1;
+      if (nb >= 2 && xs[nb] - xs[nb - 1] == 1) xs[nb - 1] -= 1;  // widths >= 2 (the previous block keeps >= 63)
+      const int H = std::max(1, std::min(inst[i].strip_rows, nyf));
+      const int sy = (nyf + H - 1) / H;
+      for (int b = 0; b < sy; ++b) {
+        const int ya = 1 + (int)((int64_t)nyf * b / sy), yb = 1 + (int)((int64_t)nyf * (b + 1) / sy);
+        for (int a = 0; a < nb; ++a) {
+          WaveTask t;
+          t.inst = i;
+          t.x0 = xs[a];
+          t.y0 = ya;
+          t.wh = (xs[a + 1] - xs[a]) | ((yb - ya) << 16);
+          tasks.push_back(t);
+        }
+      }
+    }
+    first[n()] = (int)tasks.size();
+  }
+
+  int upload_tables() {
+    if (tasks.size() > L.task_cap) return fail(LBM_E_INVALID, "task table overflow");
+    HIP_TRY(hipMemcpyAsync(d_tasks(), tasks.data(), sizeof(WaveTask) * tasks.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_first(), first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_desc(), hdesc.data(), sizeof(InstDesc) * hdesc.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return LBM_OK;
+  }
+};
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+size_t lbm_workspace_bytes(const lbm_params* p, int32_t n_inst) {
+  std::string why;
+  if (!valid_params(p, n_inst, &why)) {
+    fail(LBM_E_INVALID, "%s", why.c_str());
+    return 0;
+  }
+  return make_layout(p, n_inst).total;
+}
+
+int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws_bytes, void* hip_stream,
+               lbm_ctx** out) {
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(p, n_inst, &why)) return fail(LBM_E_INVALID, "%s", why.c_str());
+  Layout L = make_layout(p, n_inst);
+  if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(LBM_E_WORKSPACE, "workspace NULL or not 256-B aligned");
+  if (ws_bytes < L.total) return fail(LBM_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.total);
+
+  lbm_ctx* c = new lbm_ctx();
+  c->L = L;
+  c->ws = (char*)d_workspace;
+  c->ws_bytes = ws_bytes;
+  c->stream = (hipStream_t)hip_stream;
+  c->storage = p[0].precision == LBM_F64 ? STORE_F64 : STORE_F32;
+  if (c->storage == STORE_F64) {
+    c->waves = kDefaultWaves64;
+    c->prefetch = kDefaultPrefetch64;
+  }
+  if (p[0].step_variant > 0) {
+    c->waves = kWaveChoices[(p[0].step_variant - 1) % kNumWaveChoices];
+    c->prefetch = (p[0].step_variant - 1) / kNumWaveChoices == 1;
+  }
+  c->inst.resize(n_inst);
+  c->hdesc.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    Inst& I = c->inst[i];
+    I.p = p[i];
+    I.pitch = (p[i].nx + 63) / 64 * 64;
+    I.plane = (int64_t)I.pitch * (p[i].ny - 2);
+    I.strip_rows = p[i].strip_rows > 0 ? p[i].strip_rows
+                                        : (p[i].precision == LBM_F64 ? kDefaultStripRows64 : kDefaultStripRows);
+    cs_critical(p[i].eos_a, p[i].eos_b, p[i].eos_R, &I.rho_c, &I.T_c);
+    I.T = p[i].T_over_Tc * I.T_c;
+    Eos E{p[i].eos_a, p[i].eos_b, p[i].eos_R, I.T};
+    if (!cs_maxwell(E, I.rho_c, &I.rho_v, &I.rho_l)) {
+      delete c;
+      return fail(LBM_E_INVALID, "instance %d: no coexistence found", i);
+    }
+    I.rho_cap = cs_rho_cap(E, I.rho_c);
+    for (int k = 0; k < 2; ++k) I.off_f[k] = L.inst_f[k][i];
+    I.off_th = L.inst_th[i];
+    I.off_ghost = L.inst_ghost[i];
+    I.off_adj = L.inst_adj[i];
+    const int nx = p[i].nx;
+    I.cos_th.assign(2 * nx, std::cos(M_PI / 2));
+    I.cot_th.assign(2 * nx, std::cos(M_PI / 2) / std::sin(M_PI / 2));
+    I.sin_th.assign(2 * nx, 1.0);
+
+    InstDesc& d = c->hdesc[i];
+    std::memset(&d, 0, sizeof d);
+    d.f[0] = c->ws + I.off_f[0];
+    d.f[1] = c->ws + I.off_f[1];
+    double* th = (double*)(c->ws + I.off_th);
+    d.cos_th = th;
+    d.cot_th = th + 2 * nx;
+    d.sin_th = th + 4 * nx;
+    d.ghost = (double*)(c->ws + I.off_ghost);
+    d.nx = nx;
+    d.ny = p[i].ny;
+    d.pitch = I.pitch;
+    d.wet_iters = p[i].wet_iters;
+    d.plane = I.plane;
+    d.cur = 0;
+    d.RT = p[i].eos_R * I.T;
+    d.eos_a = p[i].eos_a;
+    d.eos_b4 = 0.25 * p[i].eos_b;
+    d.two_over_Gpsi = 2.0 / p[i].G;
+    d.G_f = p[i].G;
+    d.A = p[i].A;
+    d.inv_tau = 1.0 / p[i].tau;
+    d.force_pref = 1.0 - 0.5 / p[i].tau;
+    d.body_fx = p[i].body_force[0];
+    d.body_fy = p[i].body_force[1];
+    d.rho0 = p[i].precision == LBM_F32_SHIFTED ? p[i].rho0_shift : 0.0;
+    d.rho_fp64_below = p[i].precision == LBM_F64 ? 0.0 : p[i].rho_fp64_below;
+    d.rho_cap_hi = I.rho_cap * (1.0 - 1e-12);
+  }
+  c->build_tasks();
+  int rc = c->upload_tables();
+  if (rc == LBM_OK) {
+    for (int i = 0; i < n_inst; ++i) {
+      Inst& I = c->inst[i];
+      std::vector<double> th(6 * (size_t)I.p.nx);
+      std::copy(I.cos_th.begin(), I.cos_th.end(), th.begin());
+      std::copy(I.cot_th.begin(), I.cot_th.end(), th.begin() + 2 * I.p.nx);
+      std::copy(I.sin_th.begin(), I.sin_th.end(), th.begin() + 4 * I.p.nx);
+      hipError_t e = hipMemcpyAsync(c->ws + I.off_th, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice,
+                                    c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) { rc = fail(LBM_E_HIP, "theta upload: %s", hipGetErrorString(e)); break; }
+    }
+  }
+  if (rc == LBM_OK) {
+    hipError_t e = launch_zero_diag(c->d_idiag(), n_inst, c->stream);
+    if (e != hipSuccess) rc = fail(LBM_E_HIP, "zero diag: %s", hipGetErrorString(e));
+  }
+  if (rc != LBM_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+  if (!c) return fail(LBM_E_INVALID, "NULL context");
+  c->drop_graphs();
+  delete c;
+  return LBM_OK;
+}
+
+#define CHECK_INST(c, i)                                                                       \
+  do {                                                                                         \
+    if (!(c)) return fail(LBM_E_INVALID, "NULL context");                                      \
+    if ((i) < 0 || (i) >= (c)->n()) return fail(LBM_E_INVALID, "instance %d out of range", (i)); \
+  } while (0)
+
+int lbm_eos_info(const lbm_ctx* c, int32_t inst, double out[6]) {
+  if (!c) return fail(LBM_E_INVALID, "NULL context");
+  if (inst < 0 || inst >= (int)c->inst.size()) return fail(LBM_E_INVALID, "instance out of range");
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  const Inst& I = c->inst[inst];
+  out[0] = I.rho_v;
+  out[1] = I.rho_l;
+  out[2] = I.T;
+  out[3] = I.T_c;
+  out[4] = I.rho_c;
+  out[5] = I.rho_cap;
+  return LBM_OK;
+}
+
+int lbm_init_droplet(lbm_ctx* c, int32_t inst, int32_t n, const double* xc, const double* yc, const double* R,
+                     double width, double rho_l, double rho_v) {
+  CHECK_INST(c, inst);
+  if (n < 0 || n > kMaxDrops) return fail(LBM_E_INVALID, "droplet count %d outside [0, %d]", n, kMaxDrops);
+  if (n > 0 && (!xc || !yc || !R)) return fail(LBM_E_INVALID, "droplet arrays NULL");
+  if (!(width > 0) || !std::isfinite(width)) return fail(LBM_E_INVALID, "width must be > 0");
+  Inst& I = c->inst[inst];
+  if (!(rho_l > 0)) rho_l = I.rho_l;
+  if (!(rho_v > 0)) rho_v = I.rho_v;
+  if (!std::isfinite(rho_l) || !std::isfinite(rho_v)) return fail(LBM_E_INVALID, "densities not finite");
+  std::vector<double> drops(3 * (size_t)std::max(n, 1));
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(xc[k]) || !std::isfinite(yc[k]) || !std::isfinite(R[k]))
+      return fail(LBM_E_INVALID, "droplet %d not finite", k);
+    drops[3 * k] = xc[k];
+    drops[3 * k + 1] = yc[k];
+    drops[3 * k + 2] = R[k];
+  }
+  double* dd = (double*)(c->ws + c->L.drops);
+  if (n > 0) HIP_TRY(hipMemcpyAsync(dd, drops.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_init_droplets(c->storage, c->d_desc(), inst, I.p.ny - 2, I.p.nx, dd, n, width, rho_l, rho_v,
+                               c->d_rho_scratch(), c->stream));
+  HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, I.p.nx, c->stream));
+  HIP_TRY(launch_zero_diag(c->d_idiag() + inst, 1, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  I.initialized = true;
+  I.steps = 0;
+  return LBM_OK;
+}
+
+int lbm_apply_wetting(lbm_ctx* c, int32_t inst, const double* theta_bottom, const double* theta_top) {
+  CHECK_INST(c, inst);
+  Inst& I = c->inst[inst];
+  const int nx = I.p.nx;
+  const double* src[2] = {theta_bottom, theta_top};
+  for (int w = 0; w < 2; ++w) {
+    if (!src[w]) continue;
+    for (int x = 0; x < nx; ++x) {
+      const double th = src[w][x];
+      if (!(th > 0 && th < M_PI)) return fail(LBM_E_INVALID, "theta[%d][%d] = %g outside (0, pi)", w, x, th);
+    }
+  }
+  for (int w = 0; w < 2; ++w) {
+    if (!src[w]) continue;
+    for (int x = 0; x < nx; ++x) {
+      const double th = src[w][x];
+      I.cos_th[w * nx + x] = std::cos(th);
+      I.sin_th[w * nx + x] = std::sin(th);
+      I.cot_th[w * nx + x] = std::cos(th) / std::sin(th);
+    }
+  }
+  std::vector<double> th(6 * (size_t)nx);
+  std::copy(I.cos_th.begin(), I.cos_th.end(), th.begin());
+  std::copy(I.cot_th.begin(), I.cot_th.end(), th.begin() + 2 * nx);
+  std::copy(I.sin_th.begin(), I.sin_th.end(), th.begin() + 4 * nx);
+  HIP_TRY(hipMemcpyAsync(c->ws + I.off_th, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, c->stream));
+  if (I.initialized) HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, nx, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+namespace {
+
+// Queue `count` steps for the selection (task range), flips starting at 0, checks every K (0 = none) counting
+// from the first queued step, plus one after the last step if final_check.
+int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check) {
+  const int a = sel < 0 ? 0 : c->first[sel];
+  const int b = sel < 0 ? c->first[c->n()] : c->first[sel + 1];
+  const int ninst = sel < 0 ? c->n() : 1;
+  const int inst0 = sel < 0 ? 0 : sel;
+  for (int64_t i = 0; i < count; ++i) {
+    const bool chk = (K > 0 && (i + 1) % K == 0) || (final_check && i == count - 1);
+    HIP_TRY(launch_step(c->storage, chk, c->tau1(sel), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a, b - a, (int)(i & 1),
+                        c->d_wdiag() + a,
+                        c->stream));
+    if (chk)
+      HIP_TRY(launch_finalize_diag(c->d_tasks(), c->d_first(), ninst, inst0, c->d_wdiag(), c->d_idiag(),
+                                   c->d_desc(), c->stream));
+  }
+  return LBM_OK;
+}
+
+int get_graph(lbm_ctx* c, int sel, int len, int K, hipGraphExec_t* out) {
+  auto key = std::make_pair(sel, len);
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return LBM_OK;
+  }
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = queue_steps(c, sel, len, K, false);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(LBM_E_HIP, "graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(LBM_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  c->graphs[key] = ex;
+  *out = ex;
+  return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps) {
+  if (!c) return fail(LBM_E_INVALID, "NULL context");
+  if (inst < -1 || inst >= c->n()) return fail(LBM_E_INVALID, "instance %d out of range", inst);
+  if (nsteps < 0) return fail(LBM_E_INVALID, "nsteps < 0");
+  for (int i = 0; i < c->n(); ++i)
+    if ((inst < 0 || i == inst) && !c->inst[i].initialized)
+      return fail(LBM_E_STATE, "instance %d has no state (call lbm_init_droplet or lbm_set_populations)", i);
+  if (nsteps == 0) return LBM_OK;
+  const int K = c->inst[inst < 0 ? 0 : inst].p.check_every;
+  const int len = K > 0 ? (K % 2 == 0 ? K : 2 * K) : 64;
+  int64_t left = nsteps;
+  if (c->stream != nullptr && nsteps >= len && len <= 4096) {
+    hipGraphExec_t ex;
+    int rc = get_graph(c, inst, len, K, &ex);
+    if (rc != LBM_OK) return rc;
+    while (left >= len) {
+      HIP_TRY(hipGraphLaunch(ex, c->stream));
+      left -= len;
+    }
+  }
+  if (left > 0) {
+    // graph replays cover a multiple of 2 K steps, so flips restart at 0 and check positions stay aligned
+    int rc = queue_steps(c, inst, left, K, K > 0);
+    if (rc != LBM_OK) return rc;
+  }
+  if (nsteps & 1) {
+    for (int i = 0; i < c->n(); ++i) {
+      if (inst >= 0 && i != inst) continue;
+      c->hdesc[i].cur ^= 1;
+      HIP_TRY(launch_set_cur(c->d_desc(), i, c->hdesc[i].cur, c->stream));
+    }
+  }
+  for (int i = 0; i < c->n(); ++i)
+    if (inst < 0 || i == inst) c->inst[i].steps += nsteps;
+  if (K > 0) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<InstDiag> g(c->n());
+    HIP_TRY(hipMemcpy(g.data(), c->d_idiag(), sizeof(InstDiag) * c->n(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n(); ++i)
+      if ((inst < 0 || i == inst) && g[i].nonfinite > 0)
+        return fail(LBM_E_UNSTABLE, "instance %d: non-finite density at a check (%lld nodes)", i,
+                    (long long)g[i].nonfinite);
+  }
+  return LBM_OK;
+}
+
+int lbm_get_diag(lbm_ctx* c, int32_t inst, lbm_diag* out) {
+  CHECK_INST(c, inst);
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  InstDiag g;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&g, c->d_idiag() + inst, sizeof g, hipMemcpyDeviceToHost));
+  out->mass = g.mass;
+  out->checks = g.checks;
+  out->nonfinite = g.nonfinite;
+  out->psi_clamps = g.psi_clamps;
+  out->ghost_clamps = g.ghost_clamps;
+  out->steps = c->inst[inst].steps;
+  return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx* c, int32_t inst, double* out) {
+  CHECK_INST(c, inst);
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  if (!c->inst[inst].initialized) return fail(LBM_E_STATE, "no state");
+  const Inst& I = c->inst[inst];
+  HIP_TRY(launch_mass(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, c->d_partials(), kMeasureBlocks, c->stream));
+  std::vector<double> part(kMeasureBlocks);
+  HIP_TRY(hipMemcpyAsync(part.data(), c->d_partials(), sizeof(double) * kMeasureBlocks, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double m = 0.0;
+  for (double v : part) m += v;
+  *out = m;
+  return LBM_OK;
+}
+
+int lbm_get_rho(lbm_ctx* c, int32_t inst, double* dst, int32_t dst_on_device) {
+  CHECK_INST(c, inst);
+  if (!dst) return fail(LBM_E_INVALID, "dst is NULL");
+  if (!c->inst[inst].initialized) return fail(LBM_E_STATE, "no state");
+  const Inst& I = c->inst[inst];
+  const size_t n = (size_t)I.p.nx * I.p.ny;
+  double* target = dst_on_device ? dst : c->d_rho_scratch();
+  HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, I.p.nx, c->stream));
+  HIP_TRY(launch_get_rho(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, target, c->stream));
+  if (!dst_on_device) {
+    HIP_TRY(hipMemcpyAsync(dst, target, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx* c, int32_t inst, double* dst, int32_t dst_on_device) {
+  CHECK_INST(c, inst);
+  if (!dst) return fail(LBM_E_INVALID, "dst is NULL");
+  if (!c->inst[inst].initialized) return fail(LBM_E_STATE, "no state");
+  const Inst& I = c->inst[inst];
+  const size_t n = (size_t)I.p.nx * (I.p.ny - 2);
+  if (dst_on_device) {
+    HIP_TRY(launch_get_pops(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, 0, 9, dst, c->stream));
+    return LBM_OK;
+  }
+  // host destination: one population plane at a time through the density scratch ([nx][ny] doubles)
+  for (int q = 0; q < 9; ++q) {
+    HIP_TRY(launch_get_pops(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, q, q + 1, c->d_rho_scratch(), c->stream));
+    HIP_TRY(hipMemcpyAsync(dst + q * n, c->d_rho_scratch(), sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* c, int32_t inst, const double* src, int32_t src_on_device) {
+  CHECK_INST(c, inst);
+  if (!src) return fail(LBM_E_INVALID, "src is NULL");
+  Inst& I = c->inst[inst];
+  const size_t n = (size_t)I.p.nx * (I.p.ny - 2);
+  // stored plane q takes physical plane q (nodes streaming into the fluid) and plane opp(q) (wall bounce-back)
+  for (int p = 0; p < 9; ++p) {
+    const double* plane = src + p * n;
+    if (!src_on_device) {
+      HIP_TRY(hipMemcpyAsync(c->d_rho_scratch(), plane, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+      plane = c->d_rho_scratch();
+    }
+    HIP_TRY(launch_set_plane(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, p, p, plane, c->stream));
+    if (kOpp[p] != p)
+      HIP_TRY(launch_set_plane(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, kOpp[p], p, plane, c->stream));
+    if (!src_on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, I.p.nx, c->stream));
+  HIP_TRY(launch_zero_diag(c->d_idiag() + inst, 1, c->stream));
+  I.initialized = true;
+  I.steps = 0;
+  return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c, int32_t inst) {
+  if (!c || inst < 0 || inst >= (int)c->inst.size()) {
+    fail(LBM_E_INVALID, "bad context or instance");
+    return 0;
+  }
+  const Inst& I = c->inst[inst];
+  return storage_bytes(I.p.precision) * 9 * (size_t)I.pitch * (I.p.ny - 2);
+}
+
+int lbm_get_state(lbm_ctx* c, int32_t inst, void* d_dst) {
+  CHECK_INST(c, inst);
+  if (!d_dst) return fail(LBM_E_INVALID, "dst is NULL");
+  if (!c->inst[inst].initialized) return fail(LBM_E_STATE, "no state");
+  HIP_TRY(hipMemcpyAsync(d_dst, c->hdesc[inst].f[c->hdesc[inst].cur], lbm_state_bytes(c, inst),
+                         hipMemcpyDeviceToDevice, c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, int32_t inst, const void* d_src) {
+  CHECK_INST(c, inst);
+  if (!d_src) return fail(LBM_E_INVALID, "src is NULL");
+  HIP_TRY(hipMemcpyAsync(c->hdesc[inst].f[c->hdesc[inst].cur], d_src, lbm_state_bytes(c, inst),
+                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, c->inst[inst].p.nx, c->stream));
+  c->inst[inst].initialized = true;
+  return LBM_OK;
+}
+
+int lbm_measure_contact_angle(lbm_ctx* c, int32_t inst, int32_t wall, const int32_t box[4], double out[5]) {
+  CHECK_INST(c, inst);
+  if (!box || !out) return fail(LBM_E_INVALID, "box/out NULL");
+  if (wall != 0 && wall != 1) return fail(LBM_E_INVALID, "wall must be 0 or 1");
+  if (!c->inst[inst].initialized) return fail(LBM_E_STATE, "no state");
+  const Inst& I = c->inst[inst];
+  int32_t b[4] = {std::max(box[0], 0), std::min(box[1], I.p.nx), std::max(box[2], 1), std::min(box[3], I.p.ny - 1)};
+  if (b[1] - b[0] < 2 || b[3] - b[2] < 2) return fail(LBM_E_INVALID, "box too small after clipping");
+  double* rho = c->d_rho_scratch();
+  HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, I.p.nx, c->stream));
+  HIP_TRY(launch_get_rho(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, rho, c->stream));
+  HIP_TRY(launch_minmax(rho, I.p.nx, I.p.ny, b, c->d_partials(), kMeasureBlocks, c->stream));
+  std::vector<double> part(kMeasureBlocks * kMeasureMoments);
+  HIP_TRY(hipMemcpyAsync(part.data(), c->d_partials(), sizeof(double) * 2 * kMeasureBlocks, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double lo = part[0], hi = part[kMeasureBlocks];
+  for (int k = 0; k < kMeasureBlocks; ++k) {
+    lo = std::min(lo, part[k]);
+    hi = std::max(hi, part[kMeasureBlocks + k]);
+  }
+  const double mid = 0.5 * (hi + lo);
+  const double sx = 0.5 * (b[0] + b[1]), sy = 0.5 * (b[2] + b[3]);
+  HIP_TRY(launch_ca_moments(rho, I.p.nx, I.p.ny, b, wall, mid, sx, sy, c->d_partials(), kMeasureBlocks, c->stream));
+  HIP_TRY(hipMemcpyAsync(part.data(), c->d_partials(), sizeof(double) * kMeasureBlocks * kMeasureMoments,
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double m[kMeasureMoments] = {0};
+  for (int j = 0; j < kMeasureMoments; ++j)
+    for (int k = 0; k < kMeasureBlocks; ++k) m[j] += part[j * kMeasureBlocks + k];
+  if (m[0] < 3) return fail(LBM_E_INVALID, "too few interface points in the box (%g)", m[0]);
+  // Kasa normal equations for x^2 + y^2 + D x + E y + F = 0.
+  double M3[3][4] = {{m[3], m[5], m[1], -(m[6] + m[7])},
+                     {m[5], m[4], m[2], -(m[8] + m[9])},
+                     {m[1], m[2], m[0], -(m[3] + m[4])}};
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (std::fabs(M3[r][col]) > std::fabs(M3[piv][col])) piv = r;
+    if (M3[piv][col] == 0.0) return fail(LBM_E_INVALID, "degenerate circle fit");
+    if (piv != col)
+      for (int k = 0; k < 4; ++k) std::swap(M3[piv][k], M3[col][k]);
+    for (int r = col + 1; r < 3; ++r) {
+      const double f = M3[r][col] / M3[col][col];
+      for (int k = col; k < 4; ++k) M3[r][k] -= f * M3[col][k];
+    }
+  }
+  double sol[3];
+  for (int r = 2; r >= 0; --r) {
+    double v = M3[r][3];
+    for (int k = r + 1; k < 3; ++k) v -= M3[r][k] * sol[k];
+    sol[r] = v / M3[r][r];
+  }
+  const double xc = -0.5 * sol[0], yc = -0.5 * sol[1];
+  const double R = std::sqrt(xc * xc + yc * yc - sol[2]);
+  const double Xc = xc + sx, Yc = yc + sy;
+  const double yw = wall == 0 ? 0.5 : I.p.ny - 1.5;
+  double cth = wall == 0 ? (yw - Yc) / R : (Yc - yw) / R;
+  cth = std::max(-1.0, std::min(1.0, cth));
+  out[0] = std::acos(cth);
+  out[1] = R;
+  out[2] = Xc;
+  out[3] = Yc;
+  out[4] = m[0];
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen) {
+  if (!c) return fail(LBM_E_INVALID, "NULL context");
+  if (inst < -1 || inst >= c->n()) return fail(LBM_E_INVALID, "instance out of range");
+  if (trial_steps <= 0 || !chosen) return fail(LBM_E_INVALID, "trial_steps must be > 0 and chosen non-NULL");
+  for (int i = 0; i < c->n(); ++i)
+    if ((inst < 0 || i == inst) && !c->inst[i].initialized) return fail(LBM_E_STATE, "instance %d has no state", i);
+  // group the selected instances by shape; tune one representative per shape
+  std::map<std::pair<int, int>, std::vector<int>> shapes;
+  for (int i = 0; i < c->n(); ++i)
+    if (inst < 0 || i == inst) shapes[{c->inst[i].p.nx, c->inst[i].p.ny}].push_back(i);
+  const int cand[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 128};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::vector<int> saved(c->n());
+  for (int i = 0; i < c->n(); ++i) saved[i] = c->inst[i].strip_rows;
+  int last_choice = 0, best_waves_overall = c->waves;
+  bool best_pf_overall = c->prefetch;
+  int64_t biggest = -1;
+  const int saved_waves = c->waves;
+  const bool saved_pf = c->prefetch;
+  for (auto& kv : shapes) {
+    const int rep = kv.second[0];
+    const int nyf = c->inst[rep].p.ny - 2;
+    float best = 1e30f;
+    int best_h = saved[rep], best_w = saved_waves;
+    bool best_pf = saved_pf;
+    for (int pf = 0; pf < 2; ++pf) {
+      for (int wi = 0; wi < kNumWaveChoices; ++wi) {
+        const int w = kWaveChoices[wi];
+        if (w > 1 && 64 * (w / 2) >= c->inst[rep].p.nx) continue;  // more waves than columns
+        c->waves = w;
+        for (int h : cand) {
+          if (h > nyf && h != cand[0]) continue;
+          c->inst[rep].strip_rows = h;
+          c->build_tasks();
+          int rc = c->upload_tables();
+          if (rc != LBM_OK) return rc;
+          const int a = c->first[rep], b = c->first[rep + 1];
+          // warm-up, then timed trials: every launch reads the state buffer and writes the spare one (flip 0)
+          HIP_TRY(launch_step(c->storage, false, c->tau1(rep), w, pf == 1, c->d_desc(), c->d_tasks() + a, b - a, 0,
+                              c->d_wdiag() + a, c->stream));
+          HIP_TRY(hipEventRecord(e0, c->stream));
+          for (int k = 0; k < trial_steps; ++k)
+            HIP_TRY(launch_step(c->storage, false, c->tau1(rep), w, pf == 1, c->d_desc(), c->d_tasks() + a, b - a,
+                                0, c->d_wdiag() + a, c->stream));
+          HIP_TRY(hipEventRecord(e1, c->stream));
+          HIP_TRY(hipEventSynchronize(e1));
+          float ms = 0;
+          HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) { best = ms; best_h = h; best_w = w; best_pf = pf == 1; }
+        }
+      }
+    }
+    for (int i : kv.second) saved[i] = best_h;
+    last_choice = best_h;
+    const int64_t work = (int64_t)kv.first.first * (kv.first.second - 2) * (int64_t)kv.second.size();
+    if (work > biggest) { biggest = work; best_waves_overall = best_w; best_pf_overall = best_pf; }
+  }
+  c->waves = best_waves_overall;
+  c->prefetch = best_pf_overall;
+  HIP_TRY(hipEventDestroy(e0));
+  HIP_TRY(hipEventDestroy(e1));
+  for (int i = 0; i < c->n(); ++i) c->inst[i].strip_rows = saved[i];
+  c->build_tasks();
+  int rc = c->upload_tables();
+  if (rc != LBM_OK) return rc;
+  c->drop_graphs();
+  *chosen = inst >= 0 ? saved[inst] : last_choice;
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const double* d_lambda_np1,
+                     double* d_lambda_n, double* d_theta_bar, double* d_G_bar) {
+  CHECK_INST(c, inst);
+  if (!d_state_n || !d_lambda_np1 || !d_lambda_n || !d_theta_bar || !d_G_bar)
+    return fail(LBM_E_INVALID, "NULL buffer");
+  const Inst& I = c->inst[inst];
+  if (!I.p.enable_adjoint || I.p.precision != LBM_F64)
+    return fail(LBM_E_STATE, "instance %d was created without enable_adjoint (FP64)", inst);
+  const int nx = I.p.nx, ny = I.p.ny;
+  const size_t pitch = (size_t)I.pitch;
+  const size_t field = align256(sizeof(double) * pitch * ny);
+  char* base = c->ws + I.off_adj;
+  AdjScratch sc;
+  sc.rho = (double*)base;
+  sc.psi = (double*)(base + field);
+  sc.Fbar = (double*)(base + 2 * field);
+  sc.gbar = (double*)(base + 4 * field);
+  sc.part = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx));
+  sc.nparts = 4096;
+  HIP_TRY(launch_adjoint(c->d_desc(), c->hdesc[inst], inst, sc, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar,
+                         d_G_bar, c->stream));
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal structures shared by the host part (lbm_api.cpp) and the kernels (lbm_kernels.hip) of liblbm.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Per-instance constants read by every kernel (one table in device memory, indexed by instance).
+struct InstDesc {
+  void* f[2];               // population buffers, SoA [9][ny-2][pitch] of the storage type
+  const double* cos_th;     // [2][nx]: bottom row then top row
+  const double* cot_th;     // [2][nx]
+  const double* sin_th;     // [2][nx]
+  double* ghost;            // [2][nx] ghost densities written by the wetting kernel (inspection only)
+  int32_t nx, ny, pitch, wet_iters;
+  int64_t plane;            // (ny-2) * pitch elements per population
+  int32_t cur;              // buffer holding the state before a launch with flip s = 0
+  int32_t pad0;
+  double RT;                // R * T
+  double eos_a, eos_b4;     // a, b/4
+  double two_over_Gpsi;     // 2 / G (G inside psi, Eq. 10)
+  double G_f, A;            // force prefactor and hybrid parameter (Eq. 9)
+  double inv_tau, force_pref;  // 1/tau and 1 - 1/(2 tau)
+  double body_fx, body_fy;
+  double rho0;              // storage shift (0 unless shifted FP32)
+  double rho_fp64_below;    // FP32 modes: FP64 EOS below this density
+  double rho_cap_hi;        // ghost density upper clamp, rho_cap (1 - 1e-12)
+};
+
+// One block's share of a step: columns [x0, x0+width) of rows [y0, y0+nrows) of instance inst
+// (width <= 64 * waves per block, width >= 2).
+struct WaveTask {
+  int32_t inst, x0, y0, wh;  // wh = width | (nrows << 16)
+};
+
+// Per-block results of a checked step.
+struct WaveDiag {
+  double mass;
+  int32_t nonfinite, psi_clamps, ghost_clamps, pad;
+};
+
+// Per-instance accumulated diagnostics (device).
+struct InstDiag {
+  double mass;
+  long long checks, nonfinite, psi_clamps, ghost_clamps, pad;
+};
+
+enum { STORE_F64 = 0, STORE_F32 = 1 };
+
+// Launch helpers implemented in lbm_kernels.hip. All return the hipError_t of the launch.
+// waves: wavefronts per block (1, 2, 4 or 8; the tasks must have been built for it); tau1: specialised collision
+// for tau = 1 (every instance of the launch must have tau = 1).
+constexpr int kWaveChoices[] = {1, 2, 4, 8};
+constexpr int kNumWaveChoices = 4;
+// prefetch: the populations of row y+2 are loaded while row y is processed.
+hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefetch, const InstDesc* d_desc,
+                       const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, hipStream_t s);
+hipError_t launch_finalize_diag(const WaveTask* d_tasks, const int32_t* d_inst_first, int ninst_sel, int inst0,
+                                const WaveDiag* d_wdiag, InstDiag* d_idiag, const InstDesc* d_desc,
+                                hipStream_t s);
+hipError_t launch_init_droplets(int storage, const InstDesc* d_desc, int inst, int ny_fluid, int nx,
+                                const double* d_drops, int ndrops, double width, double rho_l, double rho_v,
+                                double* d_rho_scratch, hipStream_t s);
+hipError_t launch_wetting(int storage, const InstDesc* d_desc, int inst, int nx, hipStream_t s);
+hipError_t launch_get_rho(int storage, const InstDesc* d_desc, int inst, int nx, int ny, double* d_dst,
+                          hipStream_t s);
+// Population planes [q0, q1) as FP64 [q1-q0][ny-2][nx] (unshifted), and the reverse.
+hipError_t launch_get_pops(int storage, const InstDesc* d_desc, int inst, int nx, int ny, int q0, int q1,
+                           double* d_dst, hipStream_t s);
+// Stored plane q from physical plane p ([ny-2][nx] FP64): p == q fills nodes streaming into the fluid,
+// p == opp(q) the nodes bouncing back at a wall.
+hipError_t launch_set_plane(int storage, const InstDesc* d_desc, int inst, int nx, int ny, int q, int p,
+                            const double* d_src, hipStream_t s);
+hipError_t launch_mass(int storage, const InstDesc* d_desc, int inst, int nx, int ny, double* d_partials,
+                       int nblocks, hipStream_t s);
+hipError_t launch_minmax(const double* d_rho, int nx, int ny, const int32_t* box, double* d_partials,
+                         int nblocks, hipStream_t s);
+hipError_t launch_ca_moments(const double* d_rho, int nx, int ny, const int32_t* box, int wall, double rho_mid,
+                             double shift_x, double shift_y, double* d_partials, int nblocks, hipStream_t s);
+hipError_t launch_zero_diag(InstDiag* d_idiag, int n, hipStream_t s);
+hipError_t launch_set_cur(InstDesc* d_desc, int inst, int cur, hipStream_t s);
+
+// Adjoint (FP64 only).
+struct AdjScratch {
+  double* rho;    // [ny][pitch]  densities incl. ghost rows
+  double* psi;    // [ny][pitch]
+  double* Fbar;   // [2][ny][pitch]  adjoint of the force at fluid nodes
+  double* gbar;   // [2][nx]  adjoint of the ghost density (bottom, top)
+  double* part;   // reduction partials for G_bar
+  int nparts;
+};
+hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc,
+                          const double* f_n, const double* lam_np1, double* lam_n, double* theta_bar,
+                          double* G_bar, hipStream_t s);
+
+constexpr int kMeasureBlocks = 512;
+constexpr int kMeasureMoments = 10;
+
+}  // namespace lbm

@@ -1,0 +1,212 @@
+"""Python front end of liblbm: torch owns the device workspace and the stream; every step of the method runs in
+the library's HIP kernels. Argument marshalling only."""
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import _lib
+from ._lib import LbmError, Params, check, PRECISIONS
+
+
+def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=0, strip_rows=0,
+                enable_adjoint=False, step_variant=0, tau=1.0, G=-1.0, A=-0.6, eos_a=1.0, eos_b=4.0, eos_R=1.0, rho0_shift=0.0,
+                rho_fp64_below=0.0, body_force=(0.0, 0.0)):
+    """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'."""
+    p = Params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.wet_iters = int(wet_iters)
+    p.check_every = int(check_every)
+    p.strip_rows = int(strip_rows)
+    p.enable_adjoint = 1 if enable_adjoint else 0
+    p.step_variant = int(step_variant)
+    p.tau, p.G, p.A = float(tau), float(G), float(A)
+    p.eos_a, p.eos_b, p.eos_R = float(eos_a), float(eos_b), float(eos_R)
+    p.T_over_Tc = float(T_over_Tc)
+    p.rho0_shift = float(rho0_shift)
+    p.rho_fp64_below = float(rho_fp64_below)
+    p.body_force[0], p.body_force[1] = float(body_force[0]), float(body_force[1])
+    return p
+
+
+def workspace_bytes(params):
+    params = params if isinstance(params, (list, tuple)) else [params]
+    arr = (Params * len(params))(*params)
+    lib = _lib.load()
+    n = lib.lbm_workspace_bytes(arr, len(params))
+    if n == 0:
+        raise LbmError(_lib.LBM_E_INVALID, lib.lbm_last_error().decode())
+    return n
+
+
+def _dptr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class LBM:
+    """A context over one or more lattice instances (one launch per step covers every instance when
+    `step(n, inst=-1)`)."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = _lib.load()
+        self.params = list(params) if isinstance(params, (list, tuple)) else [params]
+        self.n = len(self.params)
+        self.device = torch.device(device)
+        arr = (Params * self.n)(*self.params)
+        nbytes = workspace_bytes(self.params)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        ctx = C.c_void_p()
+        check(self.lib.lbm_create(arr, self.n, C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+                                  C.byref(ctx)))
+        self.ctx = ctx
+
+    # ------------------------------------------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.stream.synchronize()
+            check(self.lib.lbm_destroy(self.ctx))
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------------------------------- setup
+    def eos_info(self, inst=0):
+        out = (C.c_double * 6)()
+        check(self.lib.lbm_eos_info(self.ctx, inst, out))
+        keys = ["rho_v", "rho_l", "T", "T_c", "rho_c", "rho_cap"]
+        return dict(zip(keys, list(out)))
+
+    def init_droplet(self, xc, yc, R, inst=0, width=5.0, rho_l=0.0, rho_v=0.0):
+        xa, xp = _dptr(np.atleast_1d(xc))
+        ya, yp = _dptr(np.atleast_1d(yc))
+        ra, rp = _dptr(np.atleast_1d(R))
+        check(self.lib.lbm_init_droplet(self.ctx, inst, len(xa), xp, yp, rp, float(width), float(rho_l),
+                                        float(rho_v)))
+
+    def apply_wetting(self, theta_bottom=None, theta_top=None, inst=0):
+        nx = self.params[inst].nx
+        args = []
+        keep = []
+        for th in (theta_bottom, theta_top):
+            if th is None:
+                args.append(None)
+            else:
+                a, p = _dptr(np.broadcast_to(np.asarray(th, np.float64), (nx,)))
+                keep.append(a)
+                args.append(p)
+        check(self.lib.lbm_apply_wetting(self.ctx, inst, args[0], args[1]))
+
+    # ------------------------------------------------------------------------------------------- stepping
+    def step(self, nsteps, inst=0):
+        check(self.lib.lbm_step(self.ctx, inst, int(nsteps)))
+
+    def autotune(self, inst=0, trial_steps=20):
+        out = C.c_int32()
+        check(self.lib.lbm_autotune(self.ctx, inst, int(trial_steps), C.byref(out)))
+        return out.value
+
+    # ------------------------------------------------------------------------------------------- readout
+    def mass(self, inst=0):
+        out = C.c_double()
+        check(self.lib.lbm_mass(self.ctx, inst, C.byref(out)))
+        return out.value
+
+    def diag(self, inst=0):
+        d = _lib.Diag()
+        check(self.lib.lbm_get_diag(self.ctx, inst, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in _lib.Diag._fields_}
+
+    def rho(self, inst=0, device=False):
+        """Density [ny, nx] (FP64) with the ghost rows; numpy array, or a torch tensor when device=True."""
+        import torch
+        p = self.params[inst]
+        if device:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty((p.ny, p.nx), dtype=torch.float64, device=self.device)
+            check(self.lib.lbm_get_rho(self.ctx, inst, C.c_void_p(out.data_ptr()), 1))
+            return out
+        out = np.empty((p.ny, p.nx), dtype=np.float64)
+        check(self.lib.lbm_get_rho(self.ctx, inst, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def populations(self, inst=0, device=False):
+        """Populations [9, ny-2, nx] (FP64, unshifted)."""
+        import torch
+        p = self.params[inst]
+        if device:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty((9, p.ny - 2, p.nx), dtype=torch.float64, device=self.device)
+            check(self.lib.lbm_get_populations(self.ctx, inst, C.c_void_p(out.data_ptr()), 1))
+            return out
+        out = np.empty((9, p.ny - 2, p.nx), dtype=np.float64)
+        check(self.lib.lbm_get_populations(self.ctx, inst, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def set_populations(self, f, inst=0):
+        import torch
+        p = self.params[inst]
+        if isinstance(f, torch.Tensor):
+            assert f.shape == (9, p.ny - 2, p.nx) and f.dtype == torch.float64 and f.is_cuda
+            f = f.contiguous()
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            check(self.lib.lbm_set_populations(self.ctx, inst, C.c_void_p(f.data_ptr()), 1))
+            f.record_stream(self.stream)
+        else:
+            a = np.ascontiguousarray(f, dtype=np.float64)
+            assert a.shape == (9, p.ny - 2, p.nx)
+            check(self.lib.lbm_set_populations(self.ctx, inst, a.ctypes.data_as(C.c_void_p), 0))
+
+    def state_bytes(self, inst=0):
+        return self.lib.lbm_state_bytes(self.ctx, inst)
+
+    def get_state(self, inst=0):
+        import torch
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(self.state_bytes(inst), dtype=torch.uint8, device=self.device)
+        check(self.lib.lbm_get_state(self.ctx, inst, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, state, inst=0):
+        import torch
+        assert state.numel() == self.state_bytes(inst)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(self.lib.lbm_set_state(self.ctx, inst, C.c_void_p(state.data_ptr())))
+        state.record_stream(self.stream)
+
+    def measure_contact_angle(self, box, wall=0, inst=0):
+        """(theta [rad], R, xc, yc, npoints) of the droplet in box = (x_lo, x_hi, y_lo, y_hi)."""
+        b = (C.c_int32 * 4)(*[int(v) for v in box])
+        out = (C.c_double * 5)()
+        check(self.lib.lbm_measure_contact_angle(self.ctx, inst, int(wall), b, out))
+        return out[0], out[1], out[2], out[3], int(out[4])
+
+    def adjoint_step(self, f_n, lam_np1, lam_n, theta_bar, G_bar, inst=0):
+        """lam_n = (df_{n+1}/df_n)^T lam_np1; theta_bar [2, nx] and G_bar [2] accumulate (device FP64 tensors)."""
+        for t in (f_n, lam_np1, lam_n, theta_bar, G_bar):
+            assert t.is_cuda and t.is_contiguous()
+        check(self.lib.lbm_adjoint_step(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),
+                                        C.c_void_p(lam_n.data_ptr()), C.c_void_p(theta_bar.data_ptr()),
+                                        C.c_void_p(G_bar.data_ptr())))
+
+
+def deg(rad):
+    return rad * 180.0 / math.pi
