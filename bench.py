@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput of the pseudo-potential LB step with geometric wetting on one MI355X.
+
+Headline workload: the 4096 x 2048 lattice at T = 0.5 T_c (density ratio ~ 725), theta = 45 deg, a wall cap of
+radius 400 plus 64 seeded free satellites, FP32 populations with the EOS evaluated in FP64 below the geometric mean
+of the coexistence densities, a device check (mass, non-finite density) every 100 steps. One bench step = one time
+step of the whole lattice (density, psi, ghost rows, force, collision, streaming) = one launch of the step kernel.
+
+Prints one JSON line: MLUPS (fluid-node updates per second / 1e6), the HBM-roofline object of the step kernel, the
+CPU reference timed on a bounded sample, and side measurements (FP64 on the same lattice, the batched 256-instance
+workload against plain per-instance launches).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_1501_05430_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_c3.json")
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def make_sim(case, precision, check_every=100, **kw):
+    import paper_1501_05430_amd as P
+    probe = P.LBM(P.make_params(16, 8, case.T_over_Tc))
+    info = probe.eos_info()
+    probe.close()
+    extra = {}
+    if precision != "f64":
+        extra["rho_fp64_below"] = math.sqrt(info["rho_v"] * info["rho_l"])
+    if precision == "f32_shifted":
+        extra["rho0_shift"] = info["rho_l"]
+    p = P.make_params(case.nx, case.ny, case.T_over_Tc, precision=precision, check_every=check_every, **extra, **kw)
+    sim = P.LBM(p)
+    sim.apply_wetting(case.theta_bottom, case.theta_top)
+    sim.init_droplet(case.xc, case.yc, case.R)
+    return sim
+
+
+def timed_steps(sim, nsteps, inst=0):
+    """HIP-event time (ms) of nsteps steps on the library's stream; returns (ms, stable)."""
+    import torch
+    import paper_1501_05430_amd as P
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    stable = True
+    try:
+        sim.step(nsteps, inst=inst)
+    except P.LbmError as e:
+        if e.code != 4:
+            raise
+        stable = False
+    e1.record(sim.stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), stable
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=20):
+    """Achievable device-copy bandwidth on this GPU (torch copy of nbytes, read + write counted)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / ms / 1e6, 1)
+
+
+def cpu_baseline(case, target_s=15.0, max_steps=400):
+    """The FP64 reference on the same lattice and initial state, timed on the host's cores."""
+    import oracle
+    sim = oracle.Sim(case.nx, case.ny, case.T_over_Tc, theta_bottom=case.theta_bottom, theta_top=case.theta_top)
+    sim.init_droplets(case.xc, case.yc, case.R)
+    t0 = time.perf_counter()
+    sim.run(1)
+    one = time.perf_counter() - t0
+    n = int(max(1, min(max_steps, target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    sim.run(n)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(case.fluid_nodes * n / dt / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{case.nx}x{case.ny} lattice (same initial state), FP64 reference, {n} steps after 1 untimed, "
+                  f"{dt:.1f} s",
+    }
+
+
+def batched_vs_plain(steps_batched=1000, steps_plain=200):
+    """256 instances (seeded sizes, angles, temperatures): one launch per step for all of them vs plain launches
+    per instance."""
+    import paper_1501_05430_amd as P
+    from paper_1501_05430_amd import workloads as W
+    cases = W.c4_batch()
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision="f32", check_every=100) for c in cases]
+    nodes = sum(c.fluid_nodes for c in cases)
+    batch = P.LBM(params)
+    for i, c in enumerate(cases):
+        batch.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
+        batch.init_droplet(c.xc, c.yc, c.R, inst=i)
+    batch.autotune(inst=-1, trial_steps=5)
+    batch.step(50, inst=-1)
+    ms_b, stable_b = timed_steps(batch, steps_batched, inst=-1)
+    batch.close()
+    # plain per-instance launches (each instance its own context and graph), same total work per step
+    sims = []
+    for c, p in zip(cases, params):
+        s = P.LBM(p)
+        s.apply_wetting(c.theta_bottom, c.theta_top)
+        s.init_droplet(c.xc, c.yc, c.R)
+        sims.append(s)
+    import torch
+    for s in sims:
+        s.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps_plain)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    mlups_b = nodes * steps_batched / ms_b / 1e3
+    mlups_p = nodes * steps_plain / dt_plain / 1e6
+    return {
+        "instances": len(cases), "fluid_nodes": nodes, "dtype": "f32",
+        "batched_mlups": round(mlups_b, 1), "batched_stable": stable_b,
+        "batched_gbs_alg": round(72 * nodes * steps_batched / ms_b / 1e6, 1),
+        "plain_sequential_mlups": round(mlups_p, 1),
+        "speedup": round(mlups_b / mlups_p, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the step kernel's block shape first (default: the library's defaults)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the method on a single MI355X "
+              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1501_05430_amd as P
+    from paper_1501_05430_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load()
+
+    case = W.c3_large()
+    copy_gbs = copy_bandwidth()
+    sim = make_sim(case, "f32", check_every=100)
+    if args.autotune:
+        sim.autotune(trial_steps=10)
+    sim.step(args.warmup)
+    ms, stable = timed_steps(sim, args.steps)
+    diag = sim.diag()
+    theta = sim.measure_contact_angle((1700, 2400, 1, 200), wall=0)
+    sim.close()
+    nodes = case.fluid_nodes
+    ms_step = ms / args.steps
+    mlups = nodes * args.steps / ms / 1e3
+    bytes_alg = 72 * nodes  # 9 FP32 populations read + 9 written per fluid node and step
+    achieved = bytes_alg / (ms_step * 1e-3) / 1e9
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha256") == kernel_sha():
+            traffic = tr.get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": "MLUPS & % HBM roofline; FP32/batched/adjoint vs plain FP64 at stated error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": case.name, "nx": case.nx, "ny": case.ny, "fluid_nodes": nodes, "T_over_Tc": 0.5,
+            "theta_deg": 45, "droplets": len(case.xc), "seed": W.SEED, "precision": "f32 (FP64 EOS in vapour)",
+            "check_every": 100, "stable": stable, "mass_at_last_check": diag["mass"],
+            "measured_theta_deg": round(math.degrees(theta[0]), 3),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "copy_gbs_on_this_gpu": copy_gbs,
+        },
+    }
+
+    if not args.no_extras:
+        sim64 = make_sim(case, "f64", check_every=100)
+        sim64.step(50)
+        ms64, st64 = timed_steps(sim64, 1000)
+        sim64.close()
+        out["extras"] = {
+            "fp64_same_lattice": {"mlups": round(nodes * 1000 / ms64 / 1e3, 1),
+                                  "gbs_alg": round(144 * nodes * 1000 / ms64 / 1e6, 1), "stable": st64},
+            "batched_256": batched_vs_plain(),
+        }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -533,3 +533,6 @@ double ora_mass(const ora_params* p, const double* f) {
 }
 
 }  // extern "C"
+
+#include <omp.h>
+extern "C" int32_t ora_num_threads(void) { return (int32_t)omp_get_max_threads(); }

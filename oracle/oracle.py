@@ -47,6 +47,7 @@ def lib():
         L.ora_psi.argtypes = [pp, d]; L.ora_psi.restype = d
         L.ora_init_droplets.argtypes = [pp, p, i32, p, p, p, d, d, d]; L.ora_init_droplets.restype = C.c_int
         L.ora_mass.argtypes = [pp, p]; L.ora_mass.restype = d
+        L.ora_num_threads.argtypes = []; L.ora_num_threads.restype = i32
         _lib = L
     return _lib
 
@@ -183,9 +184,14 @@ def collide_node(sim, f_in, Fx, Fy):
     return out
 
 
+def num_threads():
+    """OpenMP threads the reference uses."""
+    return int(lib().ora_num_threads())
+
+
 def psi(sim, rho):
     return lib().ora_psi(C.byref(sim.p), float(rho))
 
 
 __all__ = ["OraParams", "lib", "cs_pressure", "cs_dpdrho", "cs_d2pdrho2", "cs_mu", "cs_critical", "cs_maxwell",
-           "cs_rho_cap", "ghost_density", "Sim", "collide_node", "psi"]
+           "cs_rho_cap", "ghost_density", "Sim", "collide_node", "psi", "num_threads"]
