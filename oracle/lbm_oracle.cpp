@@ -21,7 +21,8 @@
 //    rows 2 and ny-3 index 2. Ghost rows carry density and psi only. Populations use halfway bounce-back.
 //  * Ghost density: Eq. (19) when wet_iters == 0; otherwise the iteration of Eq. (21) with the square root of
 //    Eq. (20) restored, stopped after exactly wet_iters iterates (the first line of Eq. (21) is iterate 1).
-//  * Ghost density is clamped to [0, rho_cap (1 - 1e-12)], where rho_cap is the largest density with real psi;
+//  * Ghost density is clamped to [0, rho_cap (1 - 1e-6)], rho_cap the largest density with real psi (psi at the
+//    clamp is then ~1e-3, not a square root of round-off, so two independent rho_cap solves agree there);
 //    psi^2 is clamped at 0 on fluid nodes. Every clamp is counted.
 #include <cmath>
 #include <complex>
@@ -327,7 +328,7 @@ struct Oracle {
       for (int x = 0; x < nx; ++x) {
         S r0 = ghost_density(rho[(size_t)r1 * nx + wrap(x - 1, nx)], rho[(size_t)r1 * nx + wrap(x + 1, nx)],
                              rho[(size_t)r1 * nx + x], rho[(size_t)r2 * nx + x], th[x], p.wet_iters);
-        double hi = rho_cap * (1.0 - 1e-12);
+        double hi = rho_cap * (1.0 - 1e-6);
         if (re(r0) < 0.0) { r0 = S(0.0); cnt.ghost_clamps++; }
         else if (re(r0) > hi) { r0 = S(hi); cnt.ghost_clamps++; }
         rho[(size_t)g * nx + x] = r0;

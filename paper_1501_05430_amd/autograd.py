@@ -1,0 +1,74 @@
+"""Differentiable rollout: torch.autograd.Function over N time steps, backward by the library's adjoint step.
+
+rho_N = Rollout(theta_bottom, theta_top, G) runs N steps from a fixed initial state with per-column wall angles
+(radians) and returns the fluid-row density [ny-2, nx] after the last step. backward() walks the steps in reverse
+with lbm_adjoint_step: the forward pass keeps an FP64 checkpoint of the populations every `seg` steps, and each
+segment is recomputed (its states kept on the device) before its adjoint steps run.
+
+G enters the model twice (the force prefactor of Eq. 9 and the G inside the psi inversion of Eq. 10); the
+gradient returned for G is their sum, the total derivative, which is zero for this model. The two parts of the
+last backward are kept in `Rollout.last_G_parts` = (dL/dG_f, dL/dG_psi).
+"""
+import numpy as np
+import torch
+
+from .lbm import LBM
+
+
+class Rollout(torch.autograd.Function):
+    last_G_parts = (0.0, 0.0)
+
+    @staticmethod
+    def forward(ctx, theta_bottom, theta_top, G, sim, f0, nsteps, seg):
+        assert isinstance(sim, LBM) and sim.params[0].enable_adjoint, "needs an LBM created with enable_adjoint"
+        assert abs(float(G) - sim.params[0].G) == 0.0, "G must equal the instance's G"
+        nsteps, seg = int(nsteps), int(seg)
+        sim.apply_wetting(theta_bottom.detach().cpu().numpy(), theta_top.detach().cpu().numpy())
+        sim.set_populations(f0)
+        checkpoints = []
+        done = 0
+        while done < nsteps:
+            checkpoints.append(sim.populations(device=True))
+            k = min(seg, nsteps - done)
+            sim.step(k)
+            done += k
+        rho = sim.rho(device=True)[1:-1].clone()
+        sim.stream.synchronize()
+        ctx.sim, ctx.nsteps, ctx.seg, ctx.checkpoints = sim, nsteps, seg, checkpoints
+        ctx.theta = (theta_bottom.detach().cpu().numpy(), theta_top.detach().cpu().numpy())
+        return rho.to(theta_bottom.device)
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        sim, nsteps, seg = ctx.sim, ctx.nsteps, ctx.seg
+        p = sim.params[0]
+        dev = sim.device
+        with torch.cuda.stream(sim.stream):
+            lam = grad_rho.detach().to(dev, torch.float64).contiguous().unsqueeze(0).expand(9, -1, -1).contiguous()
+            lam_prev = torch.empty_like(lam)
+            theta_bar = torch.zeros((2, p.nx), dtype=torch.float64, device=dev)
+            G_bar = torch.zeros(2, dtype=torch.float64, device=dev)
+        sim.apply_wetting(*ctx.theta)
+        starts = list(range(0, nsteps, seg))
+        for si in reversed(range(len(starts))):
+            k = min(seg, nsteps - starts[si])
+            sim.set_populations(ctx.checkpoints[si])
+            states = []
+            for j in range(k):
+                states.append(sim.populations(device=True))
+                if j + 1 < k:
+                    sim.step(1)
+            for j in reversed(range(k)):
+                sim.adjoint_step(states[j], lam, lam_prev, theta_bar, G_bar)
+                lam, lam_prev = lam_prev, lam
+        sim.stream.synchronize()
+        gb = G_bar.cpu().numpy()
+        Rollout.last_G_parts = (float(gb[0]), float(gb[1]))
+        tb = theta_bar.cpu()
+        ctx.checkpoints = None
+        return (tb[0].to(grad_rho.device), tb[1].to(grad_rho.device),
+                torch.tensor(float(gb[0] + gb[1]), dtype=torch.float64), None, None, None, None)
+
+
+def rollout(theta_bottom, theta_top, G, sim, f0, nsteps, seg=100):
+    return Rollout.apply(theta_bottom, theta_top, torch.as_tensor(G, dtype=torch.float64), sim, f0, nsteps, seg)

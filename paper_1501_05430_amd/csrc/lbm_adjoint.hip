@@ -1,0 +1,330 @@
+// Adjoint of one time step (FP64), for lbm_adjoint_step.
+//
+// Forward step, per fluid node x (see lbm_kernels.hip):
+//   rho = sum_i f_i, j = sum_i f_i e_i, psi = sqrt(a), a = (2/G_psi)(p_EOS(rho) - rho/3) clamped at 0 (Eq. 10);
+//   ghost rows rho_0 = W(rho_{c-1,1}, rho_{c+1,1}, rho_{c,1}, rho_{c,2}; theta_c) clamped, psi_0 = psi(rho_0)
+//   (Sec. 4, Eq. 19 / 21);
+//   F = -G_f [ (A/2) sum_a w_a psi(x+e_a)^2 e_a + (1-A) psi(x) sum_a w_a psi(x+e_a) e_a ] + F_body (Eq. 9);
+//   f*_i = (1 - 1/tau) f_i + f_eq_i(rho, v)/tau + S_i(v, F), v = (j + F/2)/rho (Eq. 1-6);
+//   f'_i(x + e_i) = f*_i(x), or f'_{opp(i)}(x) = f*_i(x) at a wall (halfway bounce-back).
+// The reverse pass, with lambda = dL/df' given:
+//   1. lambda*_i(x) = lambda_i(x + e_i) (or lambda_{opp(i)}(x) at a wall): streaming transposed, as a gather;
+//   2. collision transposed node by node: direct part of dL/df(x) and F_bar(x);
+//   3. force transposed as a gather over neighbours: psi_bar(y) from F_bar(y) and F_bar(y - e_a);
+//      G_f_bar += F_bar . (F - F_body) / G_f;
+//   4. ghost rows: psi_bar_0 -> rho_bar_0 -> wetting transposed -> theta_bar and the boundary-row densities;
+//   5. psi transposed: rho_bar(y) = psi_bar dpsi/drho, G_psi_bar += psi_bar dpsi/dG_psi; dL/df_k += rho_bar.
+// Kinks (|T| of Eq. 19, the square root at 0, the clamps) take the sub-gradient 0.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int AB = 256;          // block size
+constexpr int kAdjBlocks = 1024; // grid of the reductions (grid-stride)
+
+__device__ inline double dp_cs(const InstDesc& d, double rho) {
+  // dp/drho of Carnahan-Starling: R T (1 + 4e + 4e^2 - 4e^3 + e^4)/(1 - e)^4 - 2 a rho, e = b rho / 4
+  const double e = d.eos_b4 * rho, om = 1.0 - e;
+  const double om2 = om * om;
+  return d.RT * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om2 * om2) - 2.0 * d.eos_a * rho;
+}
+
+// d psi / d rho where psi > 0 (Eq. 10): (p'(rho) - 1/3) / (G_psi psi); 0 where psi was clamped.
+__device__ inline double dpsi_drho(const InstDesc& d, double rho, double psi) {
+  if (!(psi > 0.0)) return 0.0;
+  return (dp_cs(d, rho) - 1.0 / 3.0) * (0.5 * d.two_over_Gpsi) / psi;
+}
+
+struct Field {
+  double* p;
+  int pitch;
+  __device__ double& at(int x, int y) const { return p[(int64_t)y * pitch + x]; }
+};
+
+__device__ inline double block_sum(double v, double* sm) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sm[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < AB / 64; ++k) t += sm[k];
+  __syncthreads();
+  return t;
+}
+
+// 1. forward densities and psi at fluid nodes (physical populations f, [9][ny-2][nx])
+__global__ __launch_bounds__(AB) void ka_prep(const InstDesc* __restrict__ descs, int inst, const double* __restrict__ f,
+                                              AdjScratch sc) {
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  const int64_t n = (int64_t)nx * (ny - 2);
+  const int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x;
+  if (k >= n) return;
+  const int x = (int)(k % nx), y = (int)(k / nx) + 1;
+  double r = f[k];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) r += f[i * n + k];
+  bool cl;
+  Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
+  R.at(x, y) = r;
+  P.at(x, y) = psi_f64(d, r, cl);
+}
+
+// forward ghost rows: density (clamped), psi, and whether the clamp was active (derivative 0)
+__global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ descs, int inst, AdjScratch sc) {
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  const int t = (int)(blockIdx.x * AB + threadIdx.x);
+  if (t >= 2 * nx) return;
+  const int wall = t / nx, c = t % nx;
+  Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
+  const int g = wall == 0 ? 0 : ny - 1, r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
+  bool cl;
+  const double r0 = ghost_density(R.at(wrapx(c - 1, nx), r1), R.at(wrapx(c + 1, nx), r1), R.at(c, r1), R.at(c, r2),
+                                  d.cos_th[wall * nx + c], d.cot_th[wall * nx + c], d.wet_iters, d.rho_cap_hi, cl);
+  R.at(c, g) = r0;
+  bool dm;
+  P.at(c, g) = psi_f64(d, r0, dm);
+  sc.gflag[wall * nx + c] = cl ? 1.0 : 0.0;
+}
+
+__device__ inline void force_at(const InstDesc& d, const Field& P, int nx, int x, int y, double& Fx, double& Fy) {
+  const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
+  const double pm = P.at(x, y - 1), pmL = P.at(xl, y - 1), pmR = P.at(xr, y - 1);
+  const double pc = P.at(x, y), pcL = P.at(xl, y), pcR = P.at(xr, y);
+  const double pn = P.at(x, y + 1), pnL = P.at(xl, y + 1), pnR = P.at(xr, y + 1);
+  const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, A = d.A, Gf = d.G_f;
+  const double spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
+  const double spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
+  const double sux = k1 * (pcR * pcR - pcL * pcL) + k2 * ((pnR * pnR - pnL * pnL) + (pmR * pmR - pmL * pmL));
+  const double suy = k1 * (pn * pn - pm * pm) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
+  Fx = -Gf * (0.5 * A * sux + (1.0 - A) * pc * spx);
+  Fy = -Gf * (0.5 * A * suy + (1.0 - A) * pc * spy);
+}
+
+// 2. streaming and collision transposed; writes the direct part of lambda_n and F_bar; partials of G_f_bar
+__global__ __launch_bounds__(AB) void ka_collide(const InstDesc* __restrict__ descs, int inst,
+                                                 const double* __restrict__ f, const double* __restrict__ lam1,
+                                                 double* __restrict__ lam0, AdjScratch sc) {
+  __shared__ double sm[AB / 64];
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  const int64_t n = (int64_t)nx * (ny - 2);
+  Field P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
+  double gf_part = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x; k < n; k += (int64_t)gridDim.x * AB) {
+    const int x = (int)(k % nx), y = (int)(k / nx) + 1;
+    double fl[9], ls[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      fl[i] = f[i * n + k];
+      const int yd = y + kEY[i];
+      ls[i] = (yd < 1 || yd > ny - 2) ? lam1[kOPP[i] * n + k]
+                                      : lam1[i * n + (int64_t)(yd - 1) * nx + wrapx(x + kEX[i], nx)];
+    }
+    double Fix, Fiy;
+    force_at(d, P, nx, x, y, Fix, Fiy);
+    const double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
+    // forward collision quantities
+    double rho = fl[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) rho += fl[i];
+    const double jx = fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8];
+    const double jy = fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
+    const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
+    const double v2 = vx * vx + vy * vy;
+    const double it = d.inv_tau, pref = d.force_pref;
+    double rhob = 0.0, vbx = 0.0, vby = 0.0, Fbx = 0.0, Fby = 0.0;
+    double fb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double ex = kEX[i], ey = kEY[i], w = kW[i];
+      const double eu = ex * vx + ey * vy, eF = ex * Fx + ey * Fy;
+      fb[i] = (1.0 - it) * ls[i];
+      const double q = ls[i] * it;  // adjoint of f_eq_i
+      rhob += q * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
+      vbx += q * w * rho * (3.0 * ex + 9.0 * eu * ex - 3.0 * vx);
+      vby += q * w * rho * (3.0 * ey + 9.0 * eu * ey - 3.0 * vy);
+      const double s = ls[i] * pref * w;  // adjoint of the forcing term / (pref w)
+      vbx += s * (-3.0 * Fx + 9.0 * eF * ex);
+      vby += s * (-3.0 * Fy + 9.0 * eF * ey);
+      Fbx += s * (3.0 * ex - 3.0 * vx + 9.0 * eu * ex);
+      Fby += s * (3.0 * ey - 3.0 * vy + 9.0 * eu * ey);
+    }
+    // v = (j + F/2) / rho
+    const double jbx = vbx / rho, jby = vby / rho;
+    Fbx += 0.5 * vbx / rho;
+    Fby += 0.5 * vby / rho;
+    rhob -= (vbx * vx + vby * vy) / rho;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lam0[i * n + k] = fb[i] + rhob + jbx * kEX[i] + jby * kEY[i];
+    FX.at(x, y) = Fbx;
+    FY.at(x, y) = Fby;
+    gf_part += (Fbx * Fix + Fby * Fiy) / d.G_f;
+  }
+  const double t = block_sum(gf_part, sm);
+  if (threadIdx.x == 0) sc.part[blockIdx.x] = t;
+}
+
+// psi_bar at node y from the force of node x = y - e_a (x a fluid node): -G_f w_a (F_bar(x).e_a)(A psi(y) + (1-A) psi(x))
+__device__ inline double psi_bar_from(const InstDesc& d, const Field& P, const Field& FX, const Field& FY, int nx,
+                                      int ny, int x0, int y0) {
+  double acc = 0.0;
+  const double py = P.at(x0, y0);
+#pragma unroll
+  for (int a = 1; a < 9; ++a) {
+    const int xs = wrapx(x0 - kEX[a], nx), ys = y0 - kEY[a];
+    if (ys < 1 || ys > ny - 2) continue;
+    const double wa = a < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+    const double fe = FX.at(xs, ys) * kEX[a] + FY.at(xs, ys) * kEY[a];
+    acc += -d.G_f * wa * fe * (d.A * py + (1.0 - d.A) * P.at(xs, ys));
+  }
+  return acc;
+}
+
+// 4. ghost rows transposed: psi_bar_0 -> rho_bar_0 -> wetting -> theta_bar, boundary-row density adjoints
+//    (wet[wall][0..3][c] = d/d rho_{c-1,1}, d/d rho_{c+1,1}, d/d rho_{c,1}, d/d rho_{c,2}); partials of G_psi_bar.
+__global__ __launch_bounds__(AB) void ka_ghost_adj(const InstDesc* __restrict__ descs, int inst, AdjScratch sc,
+                                                   double* __restrict__ theta_bar) {
+  __shared__ double sm[AB / 64];
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
+  const int t = (int)(blockIdx.x * AB + threadIdx.x);
+  double gpsi = 0.0;
+  if (t < 2 * nx) {
+    const int wall = t / nx, c = t % nx;
+    const int g = wall == 0 ? 0 : ny - 1, r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
+    const double pb = psi_bar_from(d, P, FX, FY, nx, ny, c, g);
+    const double psi0 = P.at(c, g), rho0 = R.at(c, g);
+    if (psi0 > 0.0) gpsi += pb * (-psi0 * 0.5 * d.two_over_Gpsi * 0.5);  // d psi / d G_psi = -psi / (2 G_psi)
+    double rb0 = sc.gflag[wall * nx + c] != 0.0 ? 0.0 : pb * dpsi_drho(d, rho0, psi0);
+    // wetting transposed (forward recomputed)
+    const double rL = R.at(wrapx(c - 1, nx), r1), rR = R.at(wrapx(c + 1, nx), r1);
+    const double q1 = R.at(c, r1), q2 = R.at(c, r2);
+    const double cth = d.cos_th[wall * nx + c], sth = d.sin_th[wall * nx + c], cot = d.cot_th[wall * nx + c];
+    const double T = rR - rL;
+    double Tb = 0.0, Db = 0.0, thb = 0.0, q2b = rb0;
+    const int K = d.wet_iters;
+    if (K == 0) {
+      // rho_0 = rho_2 + cot(theta) |T|
+      const double sg = T > 0.0 ? 1.0 : (T < 0.0 ? -1.0 : 0.0);
+      Tb = rb0 * cot * sg;
+      thb = rb0 * fabs(T) * (-1.0 / (sth * sth));
+    } else {
+      // iterates d_1 = c sqrt(T^2 + 4 D^2), d_k = c sqrt(T^2 + d_{k-1}^2), rho_0 = rho_2 + d_K
+      const double D = q2 - q1;
+      double db = rb0;   // adjoint of d_K
+      double cb = 0.0;   // adjoint of cos(theta)
+      for (int k = K; k >= 1; --k) {
+        // forward value d_{k-1} (k >= 2) recomputed from the start
+        double dprev = 0.0;
+        if (k >= 2) {
+          dprev = cth * sqrt(T * T + 4.0 * D * D);
+          for (int m = 2; m <= k - 1; ++m) dprev = cth * sqrt(T * T + dprev * dprev);
+        }
+        const double s = k >= 2 ? sqrt(T * T + dprev * dprev) : sqrt(T * T + 4.0 * D * D);
+        cb += db * s;
+        const double sb = db * cth;
+        if (s > 0.0) {
+          Tb += sb * T / s;
+          if (k >= 2) db = sb * dprev / s;
+          else Db += sb * 4.0 * D / s;
+        } else {
+          db = 0.0;
+        }
+      }
+      thb = cb * (-sth);
+    }
+    q2b += Db;
+    const double q1b = -Db;
+    double* wet = sc.wet + wall * 4 * nx;
+    wet[0 * nx + c] = -Tb;  // d / d rho_{c-1, r1}
+    wet[1 * nx + c] = Tb;   // d / d rho_{c+1, r1}
+    wet[2 * nx + c] = q1b;  // d / d rho_{c, r1}
+    wet[3 * nx + c] = q2b;  // d / d rho_{c, r2}
+    theta_bar[wall * nx + c] += thb;
+  }
+  const double tot = block_sum(gpsi, sm);
+  if (threadIdx.x == 0) sc.part[kAdjBlocks + blockIdx.x] = tot;
+}
+
+// 5. psi transposed at fluid nodes (own force and the neighbours' forces), plus the wetting's boundary-row
+//    adjoints; lambda_n += rho_bar; partials of G_psi_bar.
+__global__ __launch_bounds__(AB) void ka_psi(const InstDesc* __restrict__ descs, int inst, double* __restrict__ lam0,
+                                             AdjScratch sc) {
+  __shared__ double sm[AB / 64];
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  const int64_t n = (int64_t)nx * (ny - 2);
+  Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
+  double gpsi = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x; k < n; k += (int64_t)gridDim.x * AB) {
+    const int x = (int)(k % nx), y = (int)(k / nx) + 1;
+    const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
+    // own force: d F(x) / d psi(x) = -G_f (1 - A) sum_a w_a psi(x + e_a) e_a
+    const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0;
+    const double spx = k1 * (P.at(xr, y) - P.at(xl, y)) + k2 * ((P.at(xr, y + 1) - P.at(xl, y + 1)) +
+                                                               (P.at(xr, y - 1) - P.at(xl, y - 1)));
+    const double spy = k1 * (P.at(x, y + 1) - P.at(x, y - 1)) + k2 * ((P.at(xr, y + 1) + P.at(xl, y + 1)) -
+                                                                     (P.at(xr, y - 1) + P.at(xl, y - 1)));
+    double pb = -d.G_f * (1.0 - d.A) * (FX.at(x, y) * spx + FY.at(x, y) * spy);
+    pb += psi_bar_from(d, P, FX, FY, nx, ny, x, y);
+    const double psi = P.at(x, y), rho = R.at(x, y);
+    if (psi > 0.0) gpsi += pb * (-psi * 0.5 * d.two_over_Gpsi * 0.5);
+    double rb = pb * dpsi_drho(d, rho, psi);
+    // boundary-row densities feed the ghost rows (bottom: rows 1, 2; top: rows ny-2, ny-3)
+    for (int wall = 0; wall < 2; ++wall) {
+      const int r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
+      const double* wet = sc.wet + wall * 4 * nx;
+      if (y == r1) rb += wet[2 * nx + x] + wet[0 * nx + xr] + wet[1 * nx + xl];
+      if (y == r2) rb += wet[3 * nx + x];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lam0[i * n + k] += rb;
+  }
+  const double tot = block_sum(gpsi, sm);
+  if (threadIdx.x == 0) sc.part[2 * kAdjBlocks + blockIdx.x] = tot;
+}
+
+// fixed-order fold of the partials into G_bar (one thread)
+__global__ void ka_finalize(AdjScratch sc, int nb_fluid, int nb_ghost, double* __restrict__ G_bar) {
+  if (threadIdx.x != 0) return;
+  double gf = 0.0, gp = 0.0;
+  for (int b = 0; b < nb_fluid; ++b) gf += sc.part[b];
+  for (int b = 0; b < nb_ghost; ++b) gp += sc.part[kAdjBlocks + b];
+  for (int b = 0; b < nb_fluid; ++b) gp += sc.part[2 * kAdjBlocks + b];
+  G_bar[0] += gf;
+  G_bar[1] += gp;
+}
+
+}  // namespace
+
+int adjoint_partials_needed() { return 3 * kAdjBlocks; }
+
+hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc,
+                          const double* f_n, const double* lam_np1, double* lam_n, double* theta_bar, double* G_bar,
+                          hipStream_t s) {
+  const int64_t n = (int64_t)h.nx * (h.ny - 2);
+  const unsigned gprep = (unsigned)((n + AB - 1) / AB);
+  const unsigned gghost = (unsigned)((2 * h.nx + AB - 1) / AB);
+  if (gghost > (unsigned)kAdjBlocks) return hipErrorInvalidValue;
+  const unsigned gred = (unsigned)std::min<int64_t>(kAdjBlocks, (n + AB - 1) / AB);
+  hipLaunchKernelGGL(ka_prep, dim3(gprep), dim3(AB), 0, s, d_desc, inst, f_n, sc);
+  hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
+  hipLaunchKernelGGL(ka_collide, dim3(gred), dim3(AB), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc);
+  hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
+  hipLaunchKernelGGL(ka_psi, dim3(gred), dim3(AB), 0, s, d_desc, inst, lam_n, sc);
+  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(64), 0, s, sc, (int)gred, (int)gghost, G_bar);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -191,7 +191,8 @@ int blocks_x(int nx, int waves) { return (nx + 64 * waves - 1) / (64 * waves); }
 size_t adj_bytes(const lbm_params& p) {
   const size_t pitch = (size_t)((p.nx + 63) / 64 * 64);
   const size_t field = align256(sizeof(double) * pitch * p.ny);
-  return 4 * field + align256(sizeof(double) * 2 * p.nx) + align256(sizeof(double) * 4 * 4096);
+  return 4 * field + align256(sizeof(double) * 2 * p.nx) + align256(sizeof(double) * 8 * p.nx) +
+         align256(sizeof(double) * adjoint_partials_needed());
 }
 
 bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
@@ -433,7 +434,7 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     d.body_fy = p[i].body_force[1];
     d.rho0 = p[i].precision == LBM_F32_SHIFTED ? p[i].rho0_shift : 0.0;
     d.rho_fp64_below = p[i].precision == LBM_F64 ? 0.0 : p[i].rho_fp64_below;
-    d.rho_cap_hi = I.rho_cap * (1.0 - 1e-12);
+    d.rho_cap_hi = I.rho_cap * (1.0 - 1e-6);
   }
   c->build_tasks();
   int rc = c->upload_tables();
@@ -917,9 +918,10 @@ int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const do
   sc.rho = (double*)base;
   sc.psi = (double*)(base + field);
   sc.Fbar = (double*)(base + 2 * field);
-  sc.gbar = (double*)(base + 4 * field);
-  sc.part = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx));
-  sc.nparts = 4096;
+  sc.gflag = (double*)(base + 4 * field);
+  sc.wet = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx));
+  sc.part = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx) + align256(sizeof(double) * 8 * nx));
+  if (2 * nx > 1024 * 256) return fail(LBM_E_UNSUPPORTED, "adjoint: nx too large");
   HIP_TRY(launch_adjoint(c->d_desc(), c->hdesc[inst], inst, sc, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar,
                          d_G_bar, c->stream));
   return LBM_OK;

@@ -24,7 +24,7 @@ struct InstDesc {
   double body_fx, body_fy;
   double rho0;              // storage shift (0 unless shifted FP32)
   double rho_fp64_below;    // FP32 modes: FP64 EOS below this density
-  double rho_cap_hi;        // ghost density upper clamp, rho_cap (1 - 1e-12)
+  double rho_cap_hi;        // ghost density upper clamp, rho_cap (1 - 1e-6)
 };
 
 // One block's share of a step: columns [x0, x0+width) of rows [y0, y0+nrows) of instance inst
@@ -80,15 +80,16 @@ hipError_t launch_ca_moments(const double* d_rho, int nx, int ny, const int32_t*
 hipError_t launch_zero_diag(InstDiag* d_idiag, int n, hipStream_t s);
 hipError_t launch_set_cur(InstDesc* d_desc, int inst, int cur, hipStream_t s);
 
-// Adjoint (FP64 only).
+// Adjoint (FP64 only): scratch carved from the workspace of an instance created with enable_adjoint.
 struct AdjScratch {
-  double* rho;    // [ny][pitch]  densities incl. ghost rows
+  double* rho;    // [ny][pitch]  densities, ghost rows included
   double* psi;    // [ny][pitch]
-  double* Fbar;   // [2][ny][pitch]  adjoint of the force at fluid nodes
-  double* gbar;   // [2][nx]  adjoint of the ghost density (bottom, top)
-  double* part;   // reduction partials for G_bar
-  int nparts;
+  double* Fbar;   // [2][ny][pitch]  adjoint of the force at fluid nodes (x then y component)
+  double* gflag;  // [2][nx]  1 where the forward ghost density was clamped
+  double* wet;    // [2][4][nx]  adjoints of the densities feeding each ghost column
+  double* part;   // [adjoint_partials_needed()] reduction partials for G_bar
 };
+int adjoint_partials_needed();
 hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc,
                           const double* f_n, const double* lam_np1, double* lam_n, double* theta_bar,
                           double* G_bar, hipStream_t s);

@@ -20,190 +20,11 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "lbm_device.h"
 #include "lbm_internal.h"
 
 namespace lbm {
 namespace {
-
-constexpr int WAVE = 64;
-constexpr int BLOCK = 256;  // block size of the auxiliary kernels
-
-template <class S>
-struct ComputeOf;
-template <>
-struct ComputeOf<double> { typedef double type; };
-template <>
-struct ComputeOf<float> { typedef float type; };
-
-// Global-address-space views: loads and stores address an SGPR base plus a 32-bit lane offset.
-template <class S>
-struct Gbl;
-template <>
-struct Gbl<float> { typedef __attribute__((address_space(1))) float T; };
-template <>
-struct Gbl<double> { typedef __attribute__((address_space(1))) double T; };
-typedef __attribute__((address_space(1))) const double GCD;
-
-__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ inline int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
-
-// ------------------------------------------------------------------------------------------------ EOS / psi
-// Carnahan-Starling p(rho) and psi = sqrt(2 (p - rho/3) / G) (Eq. 10 with c = 1); the argument is clamped at 0
-// (counted) where it is negative.
-
-// FP64 mode: IEEE division and square root.
-__device__ inline double psi_f64(const InstDesc& d, double rho, bool& clamped) {
-  const double eta = d.eos_b4 * rho;
-  const double om = 1.0 - eta;
-  const double p = rho * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) / (om * om * om) - d.eos_a * rho * rho;
-  double arg = d.two_over_Gpsi * (p - rho * (1.0 / 3.0));
-  clamped = arg < 0.0;
-  if (clamped) arg = 0.0;
-  return sqrt(arg);
-}
-
-// Hardware reciprocal / reciprocal square root refined by Newton steps (about 1 ulp of FP64): used where the
-// result is rounded to FP32 afterwards.
-__device__ inline double rcp64(double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(fma(-b, r, 1.0), r, r);
-  r = fma(fma(-b, r, 1.0), r, r);
-  return r;
-}
-__device__ inline double sqrt64(double x) {
-  if (!(x > 0.0)) return 0.0;
-  const double y = __builtin_amdgcn_rsq(x);
-  double s = x * y, h = 0.5 * y;
-  const double r = fma(-s, h, 0.5);
-  s = fma(s, r, s);
-  h = fma(h, r, h);
-  return fma(fma(-s, s, x), h, s);
-}
-
-// FP32 modes: below rho_fp64_below the EOS is evaluated in FP64 (vapour side of a large density ratio),
-// elsewhere in FP32 with the hardware reciprocal and square root.
-__device__ inline float psi_f32(const InstDesc& d, float rho, bool& clamped) {
-  if (rho < (float)d.rho_fp64_below) {
-    const double r = (double)rho;
-    const double eta = d.eos_b4 * r;
-    const double om = 1.0 - eta;
-    const double p = r * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) * rcp64(om * om * om) - d.eos_a * r * r;
-    const double arg = d.two_over_Gpsi * (p - r * (1.0 / 3.0));
-    clamped = arg < 0.0;
-    return (float)sqrt64(arg);
-  }
-  const float eta = (float)d.eos_b4 * rho;
-  const float om = 1.0f - eta;
-  const float p = rho * (float)d.RT * (1.0f + eta + eta * eta - eta * eta * eta) * __builtin_amdgcn_rcpf(om * om * om) -
-                  (float)d.eos_a * rho * rho;
-  float arg = (float)d.two_over_Gpsi * (p - rho * (1.0f / 3.0f));
-  clamped = arg < 0.0f;
-  if (clamped) arg = 0.0f;
-  return __builtin_amdgcn_sqrtf(arg);
-}
-
-__device__ inline double psi_eval(const InstDesc& d, double rho, bool& cl) { return psi_f64(d, rho, cl); }
-__device__ inline float psi_eval(const InstDesc& d, float rho, bool& cl) { return psi_f32(d, rho, cl); }
-
-// BGK collision with Guo forcing (Eq. 1-6; at tau = 1 this is the relaxation matrix diag(0,1,...,1) of Sec. 3.1):
-//   v = (j + F/2)/rho, f*_i = f_i - (f_i - f_i^eq)/tau + (1 - 1/(2 tau)) w_i [3 (e_i - v) + 9 (e_i.v) e_i] . F,
-// f_i^eq = w_i rho (1 + 3 e_i.v + 4.5 (e_i.v)^2 - 1.5 v^2). Populations may be stored shifted by w_i rho0:
-// delta = rho - rho0 replaces rho in the zeroth-order term. Opposite directions share the even part
-// (w [delta - 1.5 rho v^2 + 4.5 rho (e.v)^2 + pref (9 (e.v)(e.F) - 3 v.F)]) and differ in the sign of the odd
-// part (w [3 rho e.v + 3 pref e.F]).
-template <class C, bool TAU1>
-__device__ inline void collide(const C (&f)[9], C rho, C delta, C Fx, C Fy, C inv_tau, C pref, C irho, C (&fs)[9]) {
-  const C w0 = (C)(4.0 / 9.0), w1 = (C)(1.0 / 9.0), w2 = (C)(1.0 / 36.0);
-  const C jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  const C vx = (jx + (C)0.5 * Fx) * irho;
-  const C vy = (jy + (C)0.5 * Fy) * irho;
-  const C vF = vx * Fx + vy * Fy;
-  const C eq0 = delta - (C)1.5 * rho * (vx * vx + vy * vy);  // zeroth + second-order isotropic part of f_eq
-  const C fo0 = -(C)3 * pref * vF;                          // isotropic part of the forcing
-  const C r45 = (C)4.5 * rho, r3 = (C)3 * rho, p9 = (C)9 * pref, p3 = (C)3 * pref;
-  auto put = [&](int i, int o, C w, C eu, C eF) {
-    const C se = eq0 + r45 * eu * eu;          // even part of f_eq / w
-    const C sf = fo0 + p9 * eu * eF;           // even part of the forcing / w
-    const C ae = r3 * eu, af = p3 * eF;        // odd parts
-    if (TAU1) {
-      fs[i] = w * ((se + sf) + (ae + af));
-      fs[o] = w * ((se + sf) - (ae + af));
-    } else {
-      fs[i] = f[i] + (w * (se + ae) - f[i]) * inv_tau + w * (sf + af);
-      fs[o] = f[o] + (w * (se - ae) - f[o]) * inv_tau + w * (sf - af);
-    }
-  };
-  if (TAU1) fs[0] = w0 * (eq0 + fo0);
-  else fs[0] = f[0] + (w0 * eq0 - f[0]) * inv_tau + w0 * fo0;
-  put(1, 3, w1, vx, Fx);
-  put(2, 4, w1, vy, Fy);
-  put(5, 7, w2, vx + vy, Fx + Fy);
-  put(6, 8, w2, vy - vx, Fy - Fx);
-}
-
-// Ghost density of Sec. 4 in FP64: Eq. 19 (iters == 0) or the iters-th iterate of Eq. 21 with the square root of
-// Eq. 20. T is the tangential difference of the boundary row, D = rho_2 - rho_1. Clamped to [0, rho_cap_hi].
-__device__ inline double ghost_density(double rL, double rR, double r1, double r2, double c, double cot, int iters,
-                                       double cap_hi, bool& clamped) {
-  const double T = rR - rL;
-  double r0;
-  if (iters == 0) {
-    r0 = r2 + cot * fabs(T);
-  } else {
-    const double D = r2 - r1;
-    double dd = c * sqrt(T * T + 4.0 * D * D);
-    for (int k = 2; k <= iters; ++k) dd = c * sqrt(T * T + dd * dd);
-    r0 = r2 + dd;
-  }
-  clamped = false;
-  if (r0 < 0.0) { r0 = 0.0; clamped = true; }
-  else if (r0 > cap_hi) { r0 = cap_hi; clamped = true; }
-  return r0;
-}
-
-// Streamed populations at fluid node (x, y) (rows 1..ny-2) from the stored post-collision ones (see the file
-// header): f_i(x) = g_i(x - e_i), or g_{opp(i)}(x) where x - e_i is a ghost row (halfway bounce-back).
-template <class S, class C>
-__device__ inline void gather(const typename Gbl<S>::T* __restrict__ g, int64_t plane, int pitch, int nx, int ny,
-                              int x, int y, C (&f)[9]) {
-  typedef typename Gbl<S>::T GS;
-  const int xl = x == 0 ? nx - 1 : x - 1, xr = x + 1 == nx ? 0 : x + 1;
-  const bool bot = (y == 1), top = (y == ny - 2);
-  const unsigned rc = (unsigned)((y - 1) * pitch);
-  const unsigned rd = bot ? rc : rc - (unsigned)pitch;  // row below (unused at the bottom wall)
-  const unsigned ru = top ? rc : rc + (unsigned)pitch;  // row above (unused at the top wall)
-  auto P = [&](int q, unsigned off) -> C { return (C)((const GS*)(g + q * plane))[off]; };
-  f[0] = P(0, rc + x);
-  f[1] = P(1, rc + xl);
-  f[2] = bot ? P(4, rc + x) : P(2, rd + x);
-  f[3] = P(3, rc + xr);
-  f[4] = top ? P(2, rc + x) : P(4, ru + x);
-  f[5] = bot ? P(7, rc + x) : P(5, rd + xl);
-  f[6] = bot ? P(8, rc + x) : P(6, rd + xr);
-  f[7] = top ? P(5, rc + x) : P(7, ru + xr);
-  f[8] = top ? P(6, rc + x) : P(8, ru + xl);
-}
-
-template <class C>
-__device__ inline C sum9(const C (&f)[9]) {
-  C s = f[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) s += f[i];
-  return s;
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-__device__ inline int wave_sum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
 
 // ------------------------------------------------------------------------------------------------ step kernel
 template <class S, bool CHECK, bool TAU1, int W, bool PF>
@@ -512,10 +333,6 @@ __global__ __launch_bounds__(BLOCK) void k_init_rho(const InstDesc* __restrict__
   rho[(int64_t)y * nx + x] = r;
 }
 
-__device__ constexpr int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__device__ constexpr int kOPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-__device__ constexpr double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 
 // Rest state f_i = w_i rho stored as post-collision populations: g_i(x) = f_i(x + e_i), or f_{opp(i)}(x) where
 // x + e_i is a ghost row (the inverse of the gather).
@@ -860,11 +677,6 @@ hipError_t launch_zero_diag(InstDiag* d_idiag, int n, hipStream_t s) {
 hipError_t launch_set_cur(InstDesc* d_desc, int inst, int cur, hipStream_t s) {
   hipLaunchKernelGGL(k_set_cur, dim3(1), dim3(64), 0, s, d_desc, inst, cur);
   return hipGetLastError();
-}
-
-hipError_t launch_adjoint(const InstDesc*, const InstDesc&, int, const AdjScratch&, const double*, const double*,
-                          double*, double*, double*, hipStream_t) {
-  return hipErrorNotSupported;
 }
 
 }  // namespace lbm

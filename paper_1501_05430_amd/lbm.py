@@ -143,6 +143,7 @@ class LBM:
             with torch.cuda.stream(self.stream):
                 out = torch.empty((p.ny, p.nx), dtype=torch.float64, device=self.device)
             check(self.lib.lbm_get_rho(self.ctx, inst, C.c_void_p(out.data_ptr()), 1))
+            self._hand_over()
             return out
         out = np.empty((p.ny, p.nx), dtype=np.float64)
         check(self.lib.lbm_get_rho(self.ctx, inst, out.ctypes.data_as(C.c_void_p), 0))
@@ -156,6 +157,7 @@ class LBM:
             with torch.cuda.stream(self.stream):
                 out = torch.empty((9, p.ny - 2, p.nx), dtype=torch.float64, device=self.device)
             check(self.lib.lbm_get_populations(self.ctx, inst, C.c_void_p(out.data_ptr()), 1))
+            self._hand_over()
             return out
         out = np.empty((9, p.ny - 2, p.nx), dtype=np.float64)
         check(self.lib.lbm_get_populations(self.ctx, inst, out.ctypes.data_as(C.c_void_p), 0))
@@ -183,6 +185,7 @@ class LBM:
         with torch.cuda.stream(self.stream):
             out = torch.empty(self.state_bytes(inst), dtype=torch.uint8, device=self.device)
         check(self.lib.lbm_get_state(self.ctx, inst, C.c_void_p(out.data_ptr())))
+        self._hand_over()
         return out
 
     def set_state(self, state, inst=0):
@@ -201,11 +204,19 @@ class LBM:
 
     def adjoint_step(self, f_n, lam_np1, lam_n, theta_bar, G_bar, inst=0):
         """lam_n = (df_{n+1}/df_n)^T lam_np1; theta_bar [2, nx] and G_bar [2] accumulate (device FP64 tensors)."""
+        import torch
         for t in (f_n, lam_np1, lam_n, theta_bar, G_bar):
-            assert t.is_cuda and t.is_contiguous()
+            assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         check(self.lib.lbm_adjoint_step(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),
                                         C.c_void_p(lam_n.data_ptr()), C.c_void_p(theta_bar.data_ptr()),
                                         C.c_void_p(G_bar.data_ptr())))
+        self._hand_over()
+
+    def _hand_over(self):
+        """Make torch's current stream wait for the work queued on the library's stream (device outputs)."""
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
 
 def deg(rad):
