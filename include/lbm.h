@@ -62,7 +62,7 @@ typedef struct {
   int32_t wet_iters;      /* 0: Eq. 19; k >= 1: k-th iterate of Eq. 21 (first line = iterate 1) [4] */
   int32_t check_every;    /* steps between device checks of mass, non-finite density and clamps; 0 = none */
   int32_t strip_rows;     /* rows per wavefront strip of the step kernel; 0 = library default */
-  int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step */
+  int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step (any precision) */
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects 1, 2, 4 or 8 wavefronts (64, 128, 256 or 512
                              aligned columns) per block; 0 = library default. Instance 0's value applies to the
                              whole context (lbm_autotune may change it). Results do not depend on it (bitwise). */
@@ -163,8 +163,11 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
  * lambda_{n+1} = dL/df_{n+1} (same layout), writes lambda_n = (d f_{n+1} / d f_n)^T lambda_{n+1} to d_lambda_n
  * and ACCUMULATES d_theta_bar[2][nx] += (d f_{n+1}/d theta)^T lambda_{n+1} (bottom row then top row) and
  * d_G_bar[2] += {dL/dG_f, dL/dG_psi}, G_f being the force prefactor of Eq. 9 and G_psi the G inside Eq. 10
- * (equal in the forward model). Needs enable_adjoint = 1 and LBM_F64; runs on the context's stream. Sub-gradient
- * 0 at exact kinks (|T| of Eq. 19, the square root at 0, the clamps). Does not change the context's state. */
+ * (equal in the forward model, so their sum is the total derivative, zero for this model). Needs
+ * enable_adjoint = 1. The adjoint is evaluated in FP64 at the given state for every precision: for an FP32
+ * instance it differentiates the FP32 trajectory (pass its populations from lbm_get_populations). Runs on the
+ * context's stream; sub-gradient 0 at exact kinks (|T| of Eq. 19, the square root at 0, the clamps). Does not
+ * change the context's state. */
 int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const double* d_lambda_np1,
                      double* d_lambda_n, double* d_theta_bar, double* d_G_bar);
 

@@ -224,7 +224,6 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.precision != LBM_F32_SHIFTED && q.rho0_shift != 0) return bad("rho0_shift needs LBM_F32_SHIFTED");
     if (!std::isfinite(q.rho_fp64_below)) return bad("rho_fp64_below not finite");
     if (!std::isfinite(q.body_force[0]) || !std::isfinite(q.body_force[1])) return bad("body force not finite");
-    if (q.enable_adjoint && q.precision != LBM_F64) return bad("the adjoint needs LBM_F64");
   }
   return true;
 }
@@ -908,8 +907,8 @@ int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const do
   if (!d_state_n || !d_lambda_np1 || !d_lambda_n || !d_theta_bar || !d_G_bar)
     return fail(LBM_E_INVALID, "NULL buffer");
   const Inst& I = c->inst[inst];
-  if (!I.p.enable_adjoint || I.p.precision != LBM_F64)
-    return fail(LBM_E_STATE, "instance %d was created without enable_adjoint (FP64)", inst);
+  if (!I.p.enable_adjoint)
+    return fail(LBM_E_STATE, "instance %d was created without enable_adjoint", inst);
   const int nx = I.p.nx, ny = I.p.ny;
   const size_t pitch = (size_t)I.pitch;
   const size_t field = align256(sizeof(double) * pitch * ny);
