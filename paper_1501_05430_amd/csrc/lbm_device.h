@@ -100,9 +100,14 @@ __device__ inline float psi_eval(const InstDesc& d, float rho, bool& cl) { retur
 // delta = rho - rho0 replaces rho in the zeroth-order term. Opposite directions share the even part
 // (w [delta - 1.5 rho v^2 + 4.5 rho (e.v)^2 + pref (9 (e.v)(e.F) - 3 v.F)]) and differ in the sign of the odd
 // part (w [3 rho e.v + 3 pref e.F]).
+// The rest population is taken from mass conservation, f*_0 = f_0 + sum_{i>0} (f_i - f*_i), which equals the
+// formula above in exact arithmetic. In rounded arithmetic the node's mass then changes by one rounding of f*_0
+// only: evaluating w_0 [...] directly adds a bias every step (the rounded weights do not sum to one, and the
+// -1.5 rho v^2 term falls below the rounding unit in slow regions), which in FP32 drifts the total mass by about
+// 1e-8 per step.
 template <class C, bool TAU1>
 __device__ inline void collide(const C (&f)[9], C rho, C delta, C Fx, C Fy, C inv_tau, C pref, C irho, C (&fs)[9]) {
-  const C w0 = (C)(4.0 / 9.0), w1 = (C)(1.0 / 9.0), w2 = (C)(1.0 / 36.0);
+  const C w1 = (C)(1.0 / 9.0), w2 = (C)(1.0 / 36.0);
   const C jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
   const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
   const C vx = (jx + (C)0.5 * Fx) * irho;
@@ -123,12 +128,17 @@ __device__ inline void collide(const C (&f)[9], C rho, C delta, C Fx, C Fy, C in
       fs[o] = f[o] + (w * (se - ae) - f[o]) * inv_tau + w * (sf - af);
     }
   };
-  if (TAU1) fs[0] = w0 * (eq0 + fo0);
-  else fs[0] = f[0] + (w0 * eq0 - f[0]) * inv_tau + w0 * fo0;
   put(1, 3, w1, vx, Fx);
   put(2, 4, w1, vy, Fy);
   put(5, 7, w2, vx + vy, Fx + Fy);
   put(6, 8, w2, vy - vx, Fy - Fx);
+  {
+    // the differences must see the rounded f*_i that are stored: no fusing of their products into these sums
+#pragma clang fp contract(off)
+    const C d13 = (f[1] - fs[1]) + (f[3] - fs[3]), d24 = (f[2] - fs[2]) + (f[4] - fs[4]);
+    const C d57 = (f[5] - fs[5]) + (f[7] - fs[7]), d68 = (f[6] - fs[6]) + (f[8] - fs[8]);
+    fs[0] = f[0] + ((d13 + d24) + (d57 + d68));
+  }
 }
 
 // Ghost density of Sec. 4 in FP64: Eq. 19 (iters == 0) or the iters-th iterate of Eq. 21 with the square root of
