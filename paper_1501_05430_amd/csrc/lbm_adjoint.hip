@@ -134,11 +134,8 @@ __global__ __launch_bounds__(AB) void ka_collide(const InstDesc* __restrict__ de
     force_at(d, P, nx, x, y, Fix, Fiy);
     const double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
     // forward collision quantities
-    double rho = fl[0];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) rho += fl[i];
-    const double jx = fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8];
-    const double jy = fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
+    const double rho = sum9(fl);
+    const double jx = mom_x(fl), jy = mom_y(fl);
     const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
     const double v2 = vx * vx + vy * vy;
     const double it = d.inv_tau, pref = d.force_pref;

@@ -94,6 +94,23 @@ __device__ inline float psi_f32(const InstDesc& d, float rho, bool& clamped) {
 __device__ inline double psi_eval(const InstDesc& d, double rho, bool& cl) { return psi_f64(d, rho, cl); }
 __device__ inline float psi_eval(const InstDesc& d, float rho, bool& cl) { return psi_f32(d, rho, cl); }
 
+// Density and momentum as sums of opposite pairs: the rounded results are then exactly symmetric under the
+// mirrors x -> -x and y -> -y, as in exact arithmetic, since IEEE addition is commutative and a - b = -(b - a). A
+// left-to-right sum rounds differently at mirrored nodes and, step after step, pushes a symmetric droplet
+// sideways along its neutral translation mode. (The two diagonal pairs are joined before they meet the rest.)
+template <class C>
+__device__ inline C sum9(const C (&f)[9]) {
+  return ((f[0] + (f[1] + f[3])) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+}
+template <class C>
+__device__ inline C mom_x(const C (&f)[9]) {
+  return (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
+}
+template <class C>
+__device__ inline C mom_y(const C (&f)[9]) {
+  return (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
+}
+
 // BGK collision with Guo forcing (Eq. 1-6; at tau = 1 this is the relaxation matrix diag(0,1,...,1) of Sec. 3.1):
 //   v = (j + F/2)/rho, f*_i = f_i - (f_i - f_i^eq)/tau + (1 - 1/(2 tau)) w_i [3 (e_i - v) + 9 (e_i.v) e_i] . F,
 // f_i^eq = w_i rho (1 + 3 e_i.v + 4.5 (e_i.v)^2 - 1.5 v^2). Populations may be stored shifted by w_i rho0:
@@ -108,8 +125,7 @@ __device__ inline float psi_eval(const InstDesc& d, float rho, bool& cl) { retur
 template <class C, bool TAU1>
 __device__ inline void collide(const C (&f)[9], C rho, C delta, C Fx, C Fy, C inv_tau, C pref, C irho, C (&fs)[9]) {
   const C w1 = (C)(1.0 / 9.0), w2 = (C)(1.0 / 36.0);
-  const C jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const C jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const C jx = mom_x(f), jy = mom_y(f);
   const C vx = (jx + (C)0.5 * Fx) * irho;
   const C vy = (jy + (C)0.5 * Fy) * irho;
   const C vF = vx * Fx + vy * Fy;
@@ -184,13 +200,6 @@ __device__ inline void gather(const typename Gbl<S>::T* __restrict__ g, int64_t 
   f[8] = top ? P(6, rc + x) : P(8, ru + xl);
 }
 
-template <class C>
-__device__ inline C sum9(const C (&f)[9]) {
-  C s = f[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) s += f[i];
-  return s;
-}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll

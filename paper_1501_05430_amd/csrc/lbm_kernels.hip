@@ -185,12 +185,20 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   for (int y = y0;; ++y) {
     if (act) {
       // Interaction force, Eq. 9: F = -G_f [ (A/2) sum w psi_n^2 e + (1 - A) psi sum w psi_n e ].
-      const C spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
-      const C spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
-      const C sux = k1 * (pcR * pcR - pcL * pcL) + k2 * ((pnR * pnR - pnL * pnL) + (pmR * pmR - pmL * pmL));
-      const C suy = k1 * (pn * pn - pm * pm) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
-      const C Fx = -Gf * ((C)0.5 * A * sux + ((C)1 - A) * pc * spx) + bfx;
-      const C Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
+      C Fx, Fy;
+      {
+        // Evaluated without fused multiply-adds and with psi_R^2 - psi_L^2 = (psi_R - psi_L)(psi_R + psi_L), so
+        // the rounded force is exactly odd under x -> -x and y -> -y, as the exact one is; a fused a*a - b*b is
+        // not the negative of b*b - a*a.
+#pragma clang fp contract(off)
+        const C spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
+        const C spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
+        const C sux = k1 * ((pcR - pcL) * (pcR + pcL)) +
+                      k2 * ((pnR - pnL) * (pnR + pnL) + (pmR - pmL) * (pmR + pmL));
+        const C suy = k1 * ((pn - pm) * (pn + pm)) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
+        Fx = -Gf * ((C)0.5 * A * sux + ((C)1 - A) * pc * spx) + bfx;
+        Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
+      }
       C fs[9];
       collide<C, TAU1>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
       const unsigned off = (unsigned)((y - 1) * pitch + col);
