@@ -2,4 +2,4 @@
 contact-angle wall of Hu, Li & Uddin (arXiv:1501.05430). The method runs in liblbm.so (HIP kernels behind the
 C-ABI of include/lbm.h); this package only marshals arguments and lends torch's device memory and streams."""
 from ._lib import LbmError, Params, load  # noqa: F401
-from .lbm import LBM, make_params, workspace_bytes  # noqa: F401
+from .lbm import LBM, eos_coexistence, fp32_options, make_params, workspace_bytes  # noqa: F401

@@ -30,6 +30,28 @@ def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=
     return p
 
 
+def eos_coexistence(T_over_Tc, device="cuda:0", **eos):
+    """(rho_v, rho_l) of the library's Maxwell construction at T_over_Tc (a 16 x 8 probe context)."""
+    with LBM(make_params(16, 8, T_over_Tc, **eos), device=device) as probe:
+        info = probe.eos_info()
+    return info["rho_v"], info["rho_l"]
+
+
+def fp32_options(T_over_Tc, precision, shift="rho_v", device="cuda:0", **eos):
+    """make_params keywords of the FP32 modes: the EOS in FP64 below the geometric mean of the coexistence
+    densities, and for 'f32_shifted' the reference density rho0 of the stored f_i - w_i rho0 ('rho_v', 'rho_l' or
+    a number). The vapour density is the default shift: it keeps the vapour's populations small (their relative
+    rounding is then that of the deviation from rho_v), while the liquid's populations are no larger than
+    unshifted ones."""
+    if precision == "f64":
+        return {}
+    rv, rl = eos_coexistence(T_over_Tc, device=device, **eos)
+    out = {"rho_fp64_below": math.sqrt(rv * rl)}
+    if precision == "f32_shifted":
+        out["rho0_shift"] = {"rho_v": rv, "rho_l": rl}.get(shift, shift)
+    return out
+
+
 def workspace_bytes(params):
     params = params if isinstance(params, (list, tuple)) else [params]
     arr = (Params * len(params))(*params)

@@ -8,21 +8,14 @@ def rel_max(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
 
 
-def gpu_sim(case, precision="f64", wet_iters=4, A=-0.6, check_every=0, strip_rows=0, rho0_shift=None,
+def gpu_sim(case, precision="f64", wet_iters=4, A=-0.6, check_every=0, strip_rows=0, shift="rho_v",
             rho_fp64_below=None, enable_adjoint=False, init=True, **kw):
+    """The library on one workload. FP32 modes take their EOS threshold and shift density from the library's own
+    coexistence solve (fp32_options); shift is 'rho_v', 'rho_l' or a number."""
     import paper_1501_05430_amd as P
-    extra = {}
-    sim_probe = None
-    if precision != "f64":
-        # reference densities for the FP32 options come from the library's own coexistence solve
-        probe = P.LBM(P.make_params(case.nx, case.ny, case.T_over_Tc, precision="f64"))
-        info = probe.eos_info()
-        probe.close()
-        if precision == "f32_shifted":
-            extra["rho0_shift"] = info["rho_l"] if rho0_shift is None else rho0_shift
-        extra["rho_fp64_below"] = (math.sqrt(info["rho_v"] * info["rho_l"]) if rho_fp64_below is None
-                                   else rho_fp64_below)
-    del sim_probe
+    extra = P.fp32_options(case.T_over_Tc, precision, shift=shift)
+    if rho_fp64_below is not None and precision != "f64":
+        extra["rho_fp64_below"] = rho_fp64_below
     p = P.make_params(case.nx, case.ny, case.T_over_Tc, precision=precision, wet_iters=wet_iters, A=A,
                       check_every=check_every, strip_rows=strip_rows, enable_adjoint=enable_adjoint, **extra, **kw)
     sim = P.LBM(p)

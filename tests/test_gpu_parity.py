@@ -199,10 +199,12 @@ def test_fp32_modes_track_fp64(precision):
     sim.close()
 
 
-def test_batched_equals_single_instances_bitwise():
+@pytest.mark.parametrize("precision", ["f32", "f32_shifted"])
+def test_batched_equals_single_instances_bitwise(precision):
     import paper_1501_05430_amd as P
     cases = W.c4_batch(n=12)
-    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision="f32", check_every=50) for c in cases]
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision=precision, check_every=50,
+                            **P.fp32_options(c.T_over_Tc, precision)) for c in cases]
     batch = P.LBM(params)
     singles = []
     for i, c in enumerate(cases):
