@@ -158,6 +158,35 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
     }
 
 
+def adjoint_rate(case, calls=30):
+    """lbm_adjoint_step on the same lattice (FP64 state, a seeded random cotangent): time per reverse step. Its
+    unavoidable traffic is 216 B per node: f_n and lambda_{n+1} read, lambda_n written, 9 FP64 values each."""
+    import torch
+    sim = make_sim(case, "f64", check_every=0, enable_adjoint=True)
+    sim.step(20)
+    f = sim.populations(device=True)
+    g = torch.Generator(device=f.device)
+    g.manual_seed(1501)
+    lam1 = torch.randn(f.shape, generator=g, device=f.device, dtype=f.dtype)
+    lam0 = torch.empty_like(lam1)
+    theta_bar = torch.zeros((2, case.nx), dtype=torch.float64, device=f.device)
+    G_bar = torch.zeros(2, dtype=torch.float64, device=f.device)
+    sim.adjoint_step(f, lam1, lam0, theta_bar, G_bar)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(calls):
+        sim.adjoint_step(f, lam1, lam0, theta_bar, G_bar)
+    e1.record(sim.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    finite = bool(torch.isfinite(lam0).all().item())
+    sim.close()
+    return {"ms_per_step": round(ms, 4), "mlups": round(case.fluid_nodes / ms / 1e3, 1),
+            "gbs_alg": round(216 * case.fluid_nodes / ms / 1e6, 1), "finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,7 +266,10 @@ def main():
             "fp64_same_lattice": {"mlups": round(nodes * 1000 / ms64 / 1e3, 1),
                                   "gbs_alg": round(144 * nodes * 1000 / ms64 / 1e6, 1), "stable": st64},
             "batched_256": batched_vs_plain(),
+            "adjoint_fp64_same_lattice": adjoint_rate(case),
         }
+        out["extras"]["adjoint_fp64_same_lattice"]["vs_forward_fp64"] = round(
+            out["extras"]["adjoint_fp64_same_lattice"]["mlups"] / out["extras"]["fp64_same_lattice"]["mlups"], 3)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)

@@ -162,3 +162,33 @@ def test_c5_rollout_gradient_vs_central_fd(c5):
     # G: the force prefactor and the psi inversion cancel; a central difference in G is zero to round-off
     gf, gpsi = Rollout.last_G_parts
     assert abs(gf + gpsi) <= 1e-9 * abs(gf)
+
+
+def rollout_grad(case, sim, f0, target):
+    import torch
+    from paper_1501_05430_amd.autograd import rollout
+    tb = torch.tensor(case.theta_bottom, dtype=torch.float64, requires_grad=True)
+    tt = torch.tensor(case.theta_top, dtype=torch.float64, requires_grad=True)
+    rho = rollout(tb, tt, -1.0, sim, f0, case.steps, seg=100)
+    L = torch.linalg.norm(rho - target.to(rho.device))
+    L.backward()
+    return float(L), np.concatenate([tb.grad.numpy(), tt.grad.numpy()])
+
+
+@pytest.mark.parametrize("precision", ["f32", "f32_shifted"])
+def test_c5_gradient_of_fp32_runs_tracks_fp64(c5, precision):
+    """FP32 forward runs: the adjoint linearises the step (in FP64) around the FP32 trajectory; its gradient stays
+    close to the FP64 run's, the distance set by how far the two trajectories drift apart."""
+    import paper_1501_05430_amd as P
+    case, sim64, f0, target = c5
+    L64, g64 = rollout_grad(case, sim64, f0, target)
+    sim = P.LBM(P.make_params(case.nx, case.ny, case.T_over_Tc, precision=precision, enable_adjoint=True,
+                              **P.fp32_options(case.T_over_Tc, precision)))
+    sim.apply_wetting(case.theta_bottom, case.theta_top)
+    sim.init_droplet(case.xc, case.yc, case.R)
+    L32, g32 = rollout_grad(case, sim, sim.populations(device=True), target)
+    sim.close()
+    rel = np.abs(g32 - g64).max() / np.abs(g64).max()
+    print(f"\n  c5 {precision}: loss {L32:.6f} vs {L64:.6f}, max|g32 - g64| / max|g64| = {rel:.1e}")
+    assert abs(L32 - L64) <= 1e-5 * L64
+    assert rel <= 1e-4
