@@ -61,7 +61,8 @@ typedef struct {
   int32_t precision;      /* lbm_precision; every instance of a context must use the same one */
   int32_t wet_iters;      /* 0: Eq. 19; k >= 1: k-th iterate of Eq. 21 (first line = iterate 1) [4] */
   int32_t check_every;    /* steps between device checks of mass, non-finite density and clamps; 0 = none */
-  int32_t strip_rows;     /* rows per wavefront strip of the step kernel; 0 = library default */
+  int32_t strip_rows;     /* rows per block strip of the step kernel; 0 = library default: about two blocks per
+                             compute unit over all instances, 2..32 rows (FP32) / 2..64 (FP64) */
   int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step (any precision) */
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects 1, 2, 4 or 8 wavefronts (64, 128, 256 or 512
                              aligned columns) per block; 0 = library default. Instance 0's value applies to the

@@ -154,14 +154,18 @@ double cs_rho_cap(const Eos& E, double rho_c) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Measured defaults on MI355X for the 4096 x 2048 lattice (autotuning can refine them per context):
-// FP32 8 wavefronts per block with prefetch and 32-row strips; FP64 4 wavefronts, no prefetch, 64-row strips.
+// Measured defaults on MI355X (autotuning can refine them per context): FP32 8 wavefronts per block with
+// prefetch, FP64 4 wavefronts without. Strip height: about two blocks per compute unit over all instances,
+// rows = round(fluid nodes / (2 CUs * 64 * waves)), within [2, 32] (FP32) / [2, 64] (FP64); this matches the
+// fastest measured height on 512 x 256 up to 4096 x 2048 lattices (e.g. 32 / 64 rows at 4096 x 2048, 2 / 4 rows
+// at 1024 x 512).
 constexpr int kDefaultStripRows = 32;
 constexpr int kDefaultWaves = 8;
 constexpr bool kDefaultPrefetch = true;
 constexpr int kDefaultStripRows64 = 64;
 constexpr int kDefaultWaves64 = 4;
 constexpr bool kDefaultPrefetch64 = false;
+constexpr int kMinDefaultStripRows = 2;
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
 
@@ -434,6 +438,20 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     d.rho0 = p[i].precision == LBM_F32_SHIFTED ? p[i].rho0_shift : 0.0;
     d.rho_fp64_below = p[i].precision == LBM_F64 ? 0.0 : p[i].rho_fp64_below;
     d.rho_cap_hi = I.rho_cap * (1.0 - 1e-6);
+  }
+  {
+    // default strip height from the total work (see kDefaultStripRows)
+    int cus = 256, dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    double nodes = 0;
+    for (int i = 0; i < n_inst; ++i) nodes += (double)p[i].nx * (p[i].ny - 2);
+    const int hmax = c->storage == STORE_F64 ? kDefaultStripRows64 : kDefaultStripRows;
+    const int h = (int)std::max<long>(kMinDefaultStripRows,
+                                      std::min<long>(hmax, std::lround(nodes / (2.0 * cus * 64 * c->waves))));
+    for (int i = 0; i < n_inst; ++i)
+      if (p[i].strip_rows <= 0) c->inst[i].strip_rows = h;
   }
   c->build_tasks();
   int rc = c->upload_tables();

@@ -27,7 +27,7 @@ namespace lbm {
 namespace {
 
 // ------------------------------------------------------------------------------------------------ step kernel
-template <class S, bool CHECK, bool TAU1, int W, bool PF>
+template <class S, bool CHECK, bool TAU1, int W, bool PF, bool DOWN>
 __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ descs,
                                                    const WaveTask* __restrict__ tasks, int ntasks, int flip,
                                                    WaveDiag* __restrict__ wdiag) {
@@ -139,51 +139,66 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   const C bfx = (C)d.body_fx, bfy = (C)d.body_fy;
   const C k1 = (C)(1.0 / 3.0), k2 = (C)(1.0 / 12.0);
 
-  // Top wall: the top strip computes the ghost row's psi (with its neighbours) up front, so that the row loop
-  // itself carries no wall code.
+  // The strip's rows are walked upwards (DOWN = false) or downwards. Consecutive launches alternate, so each
+  // launch first reads the rows that the previous one wrote last, while they are still in the memory-side cache.
+  // Below, "behind", "current" and "ahead" are rows in the walking direction; the force maps them back to the rows
+  // below (y - 1) and above (y + 1).
+  constexpr int st = DOWN ? -1 : 1;
+  const int ystart = DOWN ? ylast : y0, yend = DOWN ? y0 : ylast;
+  auto fluid_row = [&](int y) { return y >= 1 && y <= ny - 2; };
+  const bool wall_start = DOWN ? (ylast == ny - 2) : (y0 == 1);  // a wall behind the first row of the walk
+  const bool wall_end = DOWN ? (y0 == 1) : (ylast == ny - 2);     // a wall ahead of the last row of the walk
+
+  // The far wall: its ghost row's psi (with its neighbours) is computed up front, so that the row loop itself
+  // carries no wall code.
   C tg = (C)0, tgL = (C)0, tgR = (C)0;
-  if (ylast == ny - 2) {
+  if (wall_end) {
+    const int yb = DOWN ? 1 : ny - 2, y2 = DOWN ? 2 : ny - 3;  // boundary row and second row of that wall
     C f1[9], f2[9], r1, r2, h1, h2, p1, p2, hp1, hp2, g_rho, hg;
     bool dm;
-    produce(ny - 2, f1, r1, p1, h1, hp1, dm);
-    produce(ny - 3, f2, r2, p2, h2, hp2, dm);
-    ghost(1, ny - 2, r1, r2, h1, h2, g_rho, tg, hg);
+    produce(yb, f1, r1, p1, h1, hp1, dm);
+    produce(y2, f2, r2, p2, h2, hp2, dm);
+    ghost(DOWN ? 0 : 1, yb, r1, r2, h1, h2, g_rho, tg, hg);
     xchg(tg, hg, tgL, tgR);
   }
 
-  // window: rows (m, c, n) = (y-1, y, y+1) when row y is processed
+  // window: rows (b, c, a) = (y - st, y, y + st) when row y is processed
   C fc[9], fn[9], fp[9];
-  C rm, rc, rn, pm, pc, pn, pmL, pmR, pcL, pcR, pnL, pnR;
-  bool cl_c = false, cl_n = false;
+  C rb, rc, ra, pb, pc, pa, pbL, pbR, pcL, pcR, paL, paR;
+  bool cl_c = false, cl_a = false;
   {
-    C hpm, hpc, hpn, hrm, hrc, hrn;
-    if (y0 == 1) {
-      produce(1, fc, rc, pc, hrc, hpc, cl_c);
-      produce(2, fn, rn, pn, hrn, hpn, cl_n);
-      ghost(0, 1, rc, rn, hrc, hrn, rm, pm, hpm);
+    C hpb, hpc, hpa, hrb, hrc, hra;
+    if (wall_start) {
+      produce(ystart, fc, rc, pc, hrc, hpc, cl_c);
+      produce(ystart + st, fn, ra, pa, hra, hpa, cl_a);
+      ghost(DOWN ? 1 : 0, ystart, rc, ra, hrc, hra, rb, pb, hpb);
     } else {
-      C fm[9];
+      C fb[9];
       bool dm;
-      produce(y0 - 1, fm, rm, pm, hrm, hpm, dm);
-      produce(y0, fc, rc, pc, hrc, hpc, cl_c);
-      if (y0 + 1 <= ny - 2) produce(y0 + 1, fn, rn, pn, hrn, hpn, cl_n);
+      produce(ystart - st, fb, rb, pb, hrb, hpb, dm);
+      produce(ystart, fc, rc, pc, hrc, hpc, cl_c);
+      if (fluid_row(ystart + st)) produce(ystart + st, fn, ra, pa, hra, hpa, cl_a);
     }
-    xchg(pm, hpm, pmL, pmR);
+    xchg(pb, hpb, pbL, pbR);
     xchg(pc, hpc, pcL, pcR);
-    if (y0 + 1 <= ny - 2) {
-      xchg(pn, hpn, pnL, pnR);
+    if (fluid_row(ystart + st)) {
+      xchg(pa, hpa, paL, paR);
     } else {
-      pn = tg; pnL = tgL; pnR = tgR;
-      cl_n = false;
+      pa = tg; paL = tgL; paR = tgR;
+      cl_a = false;
     }
   }
-  // rows read by the strip: y0-1 .. min(ylast+1, ny-2); with PF the populations of row y+2 are in flight while
-  // row y is processed
-  const int yread = ylast + 1 <= ny - 2 ? ylast + 1 : ny - 2;
-  if (PF && act && y0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, y0 + 2, fp);
+  // rows read by the strip: ystart - st .. yend + st, clipped to the fluid rows; with PF the populations of row
+  // y + 2 st are in flight while row y is processed
+  const int yread = DOWN ? (y0 - 1 >= 1 ? y0 - 1 : 1) : (ylast + 1 <= ny - 2 ? ylast + 1 : ny - 2);
+  auto readable = [&](int y) { return DOWN ? y >= yread : y <= yread; };
+  if (PF && act && readable(ystart + 2 * st)) gather<S, C>(gin, plane, pitch, nx, ny, col, ystart + 2 * st, fp);
 
-  for (int y = y0;; ++y) {
+  for (int y = ystart;; y += st) {
     if (act) {
+      // psi of the rows below (m) and above (n) row y
+      const C pm = DOWN ? pa : pb, pmL = DOWN ? paL : pbL, pmR = DOWN ? paR : pbR;
+      const C pn = DOWN ? pb : pa, pnL = DOWN ? pbL : paL, pnR = DOWN ? pbR : paR;
       // Interaction force, Eq. 9: F = -G_f [ (A/2) sum w psi_n^2 e + (1 - A) psi sum w psi_n e ].
       C Fx, Fy;
       {
@@ -213,37 +228,39 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
         psi_cl += cl_c ? 1 : 0;
       }
     }
-    if (y == ylast) break;
-    // slide the window up one row
-    rm = rc; pm = pc; pmL = pcL; pmR = pcR;
-    rc = rn; pc = pn; pcL = pnL; pcR = pnR;
-    cl_c = cl_n;
+    if (y == yend) break;
+    // slide the window one row on
+    rb = rc; pb = pc; pbL = pcL; pbR = pcR;
+    rc = ra; pc = pa; pcL = paL; pcR = paR;
+    cl_c = cl_a;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fc[i] = fn[i];
-    if (y + 2 <= ny - 2) {
+    const int ynew = y + 2 * st;  // the row entering the window
+    if (fluid_row(ynew)) {
+      C g[9];  // the halo column's populations of row ynew (edge lanes)
       if (PF) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) fn[i] = act ? fp[i] : (C)0;
-        if (act && y + 3 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, y + 3, fp);
+        if (act && readable(ynew + st)) gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + st, fp);
+        if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
       } else if (act) {
-        gather<S, C>(gin, plane, pitch, nx, ny, col, y + 2, fn);
+        gather<S, C>(gin, plane, pitch, nx, ny, col, ynew, fn);
+        if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) fn[i] = (C)0;
       }
-      rn = rho0 + sum9(fn);
-      pn = psi_eval(d, rn, cl_n);
-      C hpn = (C)0;
+      ra = rho0 + sum9(fn);
+      pa = psi_eval(d, ra, cl_a);
+      C hpa = (C)0;
       if (edge) {
-        C g[9];
-        gather<S, C>(gin, plane, pitch, nx, ny, hcol, y + 2, g);
         bool dm;
-        hpn = psi_eval(d, rho0 + sum9(g), dm);
+        hpa = psi_eval(d, rho0 + sum9(g), dm);
       }
-      xchg(pn, hpn, pnL, pnR);
+      xchg(pa, hpa, paL, paR);
     } else {
-      pn = tg; pnL = tgL; pnR = tgR;
-      cl_n = false;
+      pa = tg; paL = tgL; paR = tgR;
+      cl_a = false;
     }
   }
 
@@ -565,15 +582,23 @@ __global__ void k_set_cur(InstDesc* __restrict__ d, int inst, int cur) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+template <class S, bool CHECK, bool TAU1, bool PF, bool DOWN>
+void launch_step_d(int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc, const WaveTask* d_tasks,
+                   int ntasks, int flip, WaveDiag* d_wdiag) {
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 1, PF, DOWN>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    case 2: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 2, PF, DOWN>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    case 4: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 4, PF, DOWN>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    default: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 8, PF, DOWN>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+  }
+}
+
+// Launches with odd flip walk their strips downwards (see k_step), so consecutive steps alternate.
 template <class S, bool CHECK, bool TAU1, bool PF>
 void launch_step_w(int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc, const WaveTask* d_tasks,
                    int ntasks, int flip, WaveDiag* d_wdiag) {
-  switch (waves) {
-    case 1: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 1, PF>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-    case 2: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 2, PF>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-    case 4: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 4, PF>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-    default: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 8, PF>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-  }
+  if (flip & 1) launch_step_d<S, CHECK, TAU1, PF, true>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+  else launch_step_d<S, CHECK, TAU1, PF, false>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
 }
 
 template <class S, bool PF>
