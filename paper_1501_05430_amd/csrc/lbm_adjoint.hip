@@ -292,15 +292,23 @@ __global__ __launch_bounds__(AB) void ka_psi(const InstDesc* __restrict__ descs,
   if (threadIdx.x == 0) sc.part[2 * kAdjBlocks + blockIdx.x] = tot;
 }
 
-// fixed-order fold of the partials into G_bar (one thread)
-__global__ void ka_finalize(AdjScratch sc, int nb_fluid, int nb_ghost, double* __restrict__ G_bar) {
-  if (threadIdx.x != 0) return;
+// Fold of the partials into G_bar by one block: each thread sums a fixed strided subset in order, then a fixed
+// tree over the block, so the result does not depend on timing.
+__global__ __launch_bounds__(AB) void ka_finalize(AdjScratch sc, int nb_fluid, int nb_ghost,
+                                                  double* __restrict__ G_bar) {
+  __shared__ double sm[AB / 64];
   double gf = 0.0, gp = 0.0;
-  for (int b = 0; b < nb_fluid; ++b) gf += sc.part[b];
-  for (int b = 0; b < nb_ghost; ++b) gp += sc.part[kAdjBlocks + b];
-  for (int b = 0; b < nb_fluid; ++b) gp += sc.part[2 * kAdjBlocks + b];
-  G_bar[0] += gf;
-  G_bar[1] += gp;
+  for (int b = (int)threadIdx.x; b < nb_fluid; b += AB) {
+    gf += sc.part[b];
+    gp += sc.part[2 * kAdjBlocks + b];
+  }
+  for (int b = (int)threadIdx.x; b < nb_ghost; b += AB) gp += sc.part[kAdjBlocks + b];
+  gf = block_sum(gf, sm);
+  gp = block_sum(gp, sm);
+  if (threadIdx.x == 0) {
+    G_bar[0] += gf;
+    G_bar[1] += gp;
+  }
 }
 
 }  // namespace
@@ -320,7 +328,7 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
   hipLaunchKernelGGL(ka_collide, dim3(gred), dim3(AB), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc);
   hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
   hipLaunchKernelGGL(ka_psi, dim3(gred), dim3(AB), 0, s, d_desc, inst, lam_n, sc);
-  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(64), 0, s, sc, (int)gred, (int)gghost, G_bar);
+  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(AB), 0, s, sc, (int)gred, (int)gghost, G_bar);
   return hipGetLastError();
 }
 
