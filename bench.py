@@ -253,6 +253,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            # HBM bytes of the counters (when current) over this run's time per step
+            "traffic_gbs": round(traffic / (ms_step * 1e-3) / 1e9, 1) if traffic else None,
             "copy_gbs_on_this_gpu": copy_gbs,
         },
     }

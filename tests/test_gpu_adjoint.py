@@ -192,3 +192,56 @@ def test_c5_gradient_of_fp32_runs_tracks_fp64(c5, precision):
     print(f"\n  c5 {precision}: loss {L32:.6f} vs {L64:.6f}, max|g32 - g64| / max|g64| = {rel:.1e}")
     assert abs(L32 - L64) <= 1e-5 * L64
     assert rel <= 1e-4
+
+
+def test_c5_gradient_every_wall_angle_vs_central_fd(c5):
+    """All 2 nx wall-angle components of the 2000-step rollout gradient against central differences of the
+    GPU forward run (FP64, h = 1e-6), each within 1e-4 of the largest."""
+    case, sim, f0, target = c5
+    _, g = rollout_grad(case, sim, f0, target)
+    nx, h = case.nx, 1e-6
+    fd = np.empty(2 * nx)
+    for wall in (0, 1):
+        for c in range(nx):
+            vals = []
+            for s in (1, -1):
+                b, t = case.theta_bottom.copy(), case.theta_top.copy()
+                (b if wall == 0 else t)[c] += s * h
+                vals.append(c5_loss(case, sim, f0, target, b, t))
+            fd[wall * nx + c] = (vals[0] - vals[1]) / (2 * h)
+    err = np.abs(g - fd).max() / np.abs(fd).max()
+    print(f"\n  c5 all {2 * nx} wall angles: max|g - g_FD| / max|g_FD| = {err:.1e}")
+    assert err <= 1e-4, err
+
+
+def test_c5_gradient_vs_reference_complex_step(ora, c5):
+    """The adjoint's dL/dG_f and its derivative along one seeded random direction of all wall angles against
+    complex-step derivatives of the CPU reference over the same 2000 steps (its own initial state and target)."""
+    from paper_1501_05430_amd.autograd import Rollout
+    case, sim, f0, target = c5
+    _, g = rollout_grad(case, sim, f0, target)
+    g_f = Rollout.last_G_parts[0]
+    nx = case.nx
+    th60 = np.full(nx, W.c5_target_angle())
+    tgt = ora.Sim(nx, case.ny, case.T_over_Tc, theta_bottom=th60, theta_top=th60)
+    tgt.init_droplets(case.xc, case.yc, case.R)
+    tgt.run(case.steps)
+    rho_t = tgt.density()[0][1:-1]
+    ref = ora.Sim(nx, case.ny, case.T_over_Tc, theta_bottom=case.theta_bottom, theta_top=case.theta_top)
+    ref.init_droplets(case.xc, case.yc, case.R)
+    f_init = ref.f.copy()
+
+    def loss(fc):  # L = ||rho - rho_target||_2 continued analytically (no conjugate)
+        d = fc[1:-1].sum(axis=2) - rho_t
+        return np.sqrt((d * d).sum())
+
+    hc = 1e-30
+    fc = ref.run_cplx(case.steps, f_init, case.theta_bottom, case.theta_top, -1.0 + 1j * hc, -1.0)
+    dG = loss(fc).imag / hc
+    v = np.random.default_rng(W.SEED).standard_normal(2 * nx)
+    fc = ref.run_cplx(case.steps, f_init, case.theta_bottom + 1j * hc * v[:nx], case.theta_top + 1j * hc * v[nx:],
+                      -1.0, -1.0)
+    dv = loss(fc).imag / hc
+    print(f"\n  c5 dL/dG_f: adjoint {g_f:.10e} reference {dG:.10e}; along v: adjoint {g @ v:.10e} reference {dv:.10e}")
+    assert abs(g_f - dG) <= 1e-4 * abs(dG)
+    assert abs(g @ v - dv) <= 1e-4 * abs(dv)

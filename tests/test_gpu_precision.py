@@ -183,3 +183,20 @@ def test_free_droplet_stays_mirror_symmetric_bitwise(precision):
         assert np.array_equal(rho, mirrored(rho, 1)), n
         assert np.array_equal(rho, mirrored(rho, 0)), n
     sim.close()
+
+
+@pytest.mark.parametrize("deg", [60, 90, 120])
+def test_c2_measured_angle_settles_near_prescribed(deg):
+    """The whole scheme against its own target: after 100 000 steps (FP64, settled to 0.01 deg between 100k and
+    300k steps) the fitted contact angle is within 3 deg of the prescribed one. (30 deg settles at 33.0 deg, and a
+    150 deg droplet keeps oscillating between about 146 and 160 deg at this resolution; both are reported, not
+    tested.)"""
+    case = W.c2_angle(deg)
+    sim = gpu_sim(case, precision="f64", check_every=10000)
+    sim.step(100000)
+    th = math.degrees(sim.measure_contact_angle((0, case.nx, 1, 480), 0)[0])
+    d = sim.diag()
+    sim.close()
+    print(f"\n  c2 theta={deg}: measured {th:.2f} deg after 100 000 steps")
+    assert d["nonfinite"] == 0 and d["ghost_clamps"] == 0
+    assert abs(th - deg) <= 3.0, th
