@@ -154,9 +154,12 @@ size_t lbm_state_bytes(const lbm_ctx* c, int32_t inst);
 int lbm_get_state(lbm_ctx* c, int32_t inst, void* d_dst);
 int lbm_set_state(lbm_ctx* c, int32_t inst, const void* d_src);
 
-/* Choose strip_rows for the step kernel by timing trial launches of each candidate on the current state (the
- * state is not modified: trials read the current buffer and write the spare one). trial_steps > 0 launches per
- * candidate. inst = -1 tunes the batched launch. *chosen receives the rows per strip. Synchronizes. */
+/* Choose the step kernel's shape (wavefronts per block, prefetch: context-wide) and the rows per strip by timing
+ * the launch that lbm_step(inst) runs on the current state, for every candidate: first one strip height for the
+ * whole selection, then, with several lattice shapes in the selection (inst = -1), each shape's height in turn.
+ * The state is not modified (trials read the current buffer and write the spare one). trial_steps > 0 timed
+ * launches per candidate. *chosen receives the rows per strip of inst (of instance 0 for inst = -1).
+ * Synchronizes. */
 int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen);
 
 /* Adjoint of one time step (the reverse of streaming, collision, force, wetting and psi, in that order).

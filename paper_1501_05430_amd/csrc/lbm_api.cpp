@@ -853,69 +853,87 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   if (trial_steps <= 0 || !chosen) return fail(LBM_E_INVALID, "trial_steps must be > 0 and chosen non-NULL");
   for (int i = 0; i < c->n(); ++i)
     if ((inst < 0 || i == inst) && !c->inst[i].initialized) return fail(LBM_E_STATE, "instance %d has no state", i);
-  // group the selected instances by shape; tune one representative per shape
-  std::map<std::pair<int, int>, std::vector<int>> shapes;
+  // The selection is timed as it runs: one launch over all its tasks. Trial launches read the state buffer and
+  // write the spare one (flip 0), walking up and down alternately, so the state is not modified.
+  std::vector<int> sel;
+  int max_nx = 0, max_nyf = 0;
   for (int i = 0; i < c->n(); ++i)
-    if (inst < 0 || i == inst) shapes[{c->inst[i].p.nx, c->inst[i].p.ny}].push_back(i);
+    if (inst < 0 || i == inst) {
+      sel.push_back(i);
+      max_nx = std::max(max_nx, c->inst[i].p.nx);
+      max_nyf = std::max(max_nyf, c->inst[i].p.ny - 2);
+    }
+  std::map<std::pair<int, int>, std::vector<int>> shapes;  // shape classes of the selection
+  for (int i : sel) shapes[{c->inst[i].p.nx, c->inst[i].p.ny}].push_back(i);
   const int cand[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 128};
+  std::vector<int> saved(c->n());
+  for (int i = 0; i < c->n(); ++i) saved[i] = c->inst[i].strip_rows;
+  const int saved_waves = c->waves;
+  const bool saved_pf = c->prefetch;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  std::vector<int> saved(c->n());
-  for (int i = 0; i < c->n(); ++i) saved[i] = c->inst[i].strip_rows;
-  int last_choice = 0, best_waves_overall = c->waves;
-  bool best_pf_overall = c->prefetch;
-  int64_t biggest = -1;
-  const int saved_waves = c->waves;
-  const bool saved_pf = c->prefetch;
-  for (auto& kv : shapes) {
-    const int rep = kv.second[0];
-    const int nyf = c->inst[rep].p.ny - 2;
-    float best = 1e30f;
-    int best_h = saved[rep], best_w = saved_waves;
-    bool best_pf = saved_pf;
-    for (int pf = 0; pf < 2; ++pf) {
-      for (int wi = 0; wi < kNumWaveChoices; ++wi) {
-        const int w = kWaveChoices[wi];
-        if (w > 1 && 64 * (w / 2) >= c->inst[rep].p.nx) continue;  // more waves than columns
+  auto trial = [&](float* ms) -> int {
+    c->build_tasks();
+    int rc = c->upload_tables();
+    if (rc != LBM_OK) return rc;
+    const int a = c->first[sel.front()], b = c->first[sel.back() + 1];
+    for (int k = 0; k <= trial_steps; ++k) {
+      if (k == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // launch 0 warms up
+      HIP_TRY(launch_step(c->storage, false, c->tau1(inst), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a,
+                          b - a, 0, c->d_wdiag() + a, c->stream, k & 1));
+    }
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    *ms = 0;
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    return LBM_OK;
+  };
+  // 1. wavefronts per block, prefetch and one strip height for the whole selection
+  float best = 1e30f;
+  int best_w = saved_waves, best_h = saved[sel.front()];
+  bool best_pf = saved_pf;
+  for (int pf = 0; pf < 2; ++pf)
+    for (int wi = 0; wi < kNumWaveChoices; ++wi) {
+      const int w = kWaveChoices[wi];
+      if (w > 1 && 64 * (w / 2) >= max_nx) continue;  // more waves than columns
+      for (int h : cand) {
+        if (h > max_nyf && h != cand[0]) continue;
         c->waves = w;
-        for (int h : cand) {
-          if (h > nyf && h != cand[0]) continue;
-          c->inst[rep].strip_rows = h;
-          c->build_tasks();
-          int rc = c->upload_tables();
-          if (rc != LBM_OK) return rc;
-          const int a = c->first[rep], b = c->first[rep + 1];
-          // warm-up, then timed trials: every launch reads the state buffer and writes the spare one (flip 0)
-          HIP_TRY(launch_step(c->storage, false, c->tau1(rep), w, pf == 1, c->d_desc(), c->d_tasks() + a, b - a, 0,
-                              c->d_wdiag() + a, c->stream));
-          HIP_TRY(hipEventRecord(e0, c->stream));
-          for (int k = 0; k < trial_steps; ++k)
-            HIP_TRY(launch_step(c->storage, false, c->tau1(rep), w, pf == 1, c->d_desc(), c->d_tasks() + a, b - a,
-                                0, c->d_wdiag() + a, c->stream));
-          HIP_TRY(hipEventRecord(e1, c->stream));
-          HIP_TRY(hipEventSynchronize(e1));
-          float ms = 0;
-          HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-          if (ms < best) { best = ms; best_h = h; best_w = w; best_pf = pf == 1; }
-        }
+        c->prefetch = pf == 1;
+        for (int i : sel) c->inst[i].strip_rows = h;
+        float ms;
+        int rc = trial(&ms);
+        if (rc != LBM_OK) return rc;
+        if (ms < best) { best = ms; best_w = w; best_pf = pf == 1; best_h = h; }
       }
     }
-    for (int i : kv.second) saved[i] = best_h;
-    last_choice = best_h;
-    const int64_t work = (int64_t)kv.first.first * (kv.first.second - 2) * (int64_t)kv.second.size();
-    if (work > biggest) { biggest = work; best_waves_overall = best_w; best_pf_overall = best_pf; }
+  c->waves = best_w;
+  c->prefetch = best_pf;
+  for (int i : sel) c->inst[i].strip_rows = best_h;
+  // 2. with several shape classes, refine each class's strip height in turn (the others held)
+  if (shapes.size() > 1) {
+    for (auto& kv : shapes) {
+      const int nyf = kv.first.second - 2;
+      int keep = c->inst[kv.second.front()].strip_rows;
+      for (int h : cand) {
+        if ((h > nyf && h != cand[0]) || h == keep) continue;
+        for (int i : kv.second) c->inst[i].strip_rows = h;
+        float ms;
+        int rc = trial(&ms);
+        if (rc != LBM_OK) return rc;
+        if (ms < best) { best = ms; keep = h; }
+      }
+      for (int i : kv.second) c->inst[i].strip_rows = keep;
+    }
   }
-  c->waves = best_waves_overall;
-  c->prefetch = best_pf_overall;
   HIP_TRY(hipEventDestroy(e0));
   HIP_TRY(hipEventDestroy(e1));
-  for (int i = 0; i < c->n(); ++i) c->inst[i].strip_rows = saved[i];
   c->build_tasks();
   int rc = c->upload_tables();
   if (rc != LBM_OK) return rc;
   c->drop_graphs();
-  *chosen = inst >= 0 ? saved[inst] : last_choice;
+  *chosen = c->inst[inst >= 0 ? inst : sel.front()].strip_rows;
   return LBM_OK;
 }
 

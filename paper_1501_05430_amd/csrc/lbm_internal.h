@@ -53,8 +53,10 @@ enum { STORE_F64 = 0, STORE_F32 = 1 };
 constexpr int kWaveChoices[] = {1, 2, 4, 8};
 constexpr int kNumWaveChoices = 4;
 // prefetch: the populations of row y+2 are loaded while row y is processed.
+// down < 0: odd flips walk the strips downwards (consecutive steps alternate); 0 / 1 force up / down.
 hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefetch, const InstDesc* d_desc,
-                       const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, hipStream_t s);
+                       const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, hipStream_t s,
+                       int down = -1);
 hipError_t launch_finalize_diag(const WaveTask* d_tasks, const int32_t* d_inst_first, int ninst_sel, int inst0,
                                 const WaveDiag* d_wdiag, InstDiag* d_idiag, const InstDesc* d_desc,
                                 hipStream_t s);

@@ -593,23 +593,23 @@ void launch_step_d(int waves, unsigned grid, hipStream_t s, const InstDesc* d_de
   }
 }
 
-// Launches with odd flip walk their strips downwards (see k_step), so consecutive steps alternate.
+// down: walk the strips downwards (see k_step)
 template <class S, bool CHECK, bool TAU1, bool PF>
 void launch_step_w(int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc, const WaveTask* d_tasks,
-                   int ntasks, int flip, WaveDiag* d_wdiag) {
-  if (flip & 1) launch_step_d<S, CHECK, TAU1, PF, true>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+                   int ntasks, int flip, WaveDiag* d_wdiag, bool down) {
+  if (down) launch_step_d<S, CHECK, TAU1, PF, true>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
   else launch_step_d<S, CHECK, TAU1, PF, false>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
 }
 
 template <class S, bool PF>
 void launch_step_s(bool check, bool tau1, int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc,
-                   const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag) {
+                   const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, bool down) {
   if (check) {
-    if (tau1) launch_step_w<S, true, true, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
-    else launch_step_w<S, true, false, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+    if (tau1) launch_step_w<S, true, true, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
+    else launch_step_w<S, true, false, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
   } else {
-    if (tau1) launch_step_w<S, false, true, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
-    else launch_step_w<S, false, false, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+    if (tau1) launch_step_w<S, false, true, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
+    else launch_step_w<S, false, false, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
   }
 }
 
@@ -617,15 +617,16 @@ void launch_step_s(bool check, bool tau1, int waves, unsigned grid, hipStream_t 
 
 // ------------------------------------------------------------------------------------------------ launchers
 hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefetch, const InstDesc* d_desc,
-                       const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, hipStream_t s) {
+                       const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, hipStream_t s, int down) {
   if (ntasks <= 0) return hipSuccess;
   const unsigned grid = (unsigned)ntasks;
+  const bool dn = down < 0 ? (flip & 1) != 0 : down != 0;  // consecutive steps alternate by default
   if (storage == STORE_F64) {
-    if (prefetch) launch_step_s<double, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
-    else launch_step_s<double, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+    if (prefetch) launch_step_s<double, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    else launch_step_s<double, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
   } else {
-    if (prefetch) launch_step_s<float, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
-    else launch_step_s<float, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+    if (prefetch) launch_step_s<float, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    else launch_step_s<float, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
   }
   return hipGetLastError();
 }

@@ -219,3 +219,28 @@ def test_batched_equals_single_instances_bitwise(precision):
         assert np.array_equal(batch.populations(inst=i), s.populations()), i
         s.close()
     batch.close()
+
+
+@pytest.mark.parametrize("inst", [-1, 3])
+def test_autotune_keeps_state_and_results(inst):
+    import paper_1501_05430_amd as P
+    cases = W.c4_batch(n=10)
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision="f32_shifted", check_every=20,
+                            **P.fp32_options(c.T_over_Tc, "f32_shifted")) for c in cases]
+    sims = [P.LBM(params), P.LBM(params)]
+    for s in sims:
+        for i, c in enumerate(cases):
+            s.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
+            s.init_droplet(c.xc, c.yc, c.R, inst=i)
+        s.step(7, inst=-1)
+    before = [sims[0].populations(inst=i) for i in range(len(cases))]
+    rows = sims[0].autotune(inst=inst, trial_steps=2)
+    assert rows >= 1
+    for i in range(len(cases)):
+        assert np.array_equal(sims[0].populations(inst=i), before[i]), i
+    for s in sims:
+        s.step(40, inst=-1)
+    for i in range(len(cases)):
+        assert np.array_equal(sims[0].populations(inst=i), sims[1].populations(inst=i)), i
+    for s in sims:
+        s.close()
