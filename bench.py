@@ -109,7 +109,40 @@ def cpu_baseline(case, target_s=15.0, max_steps=400):
         "kind": "oracle",
         "sample": f"{case.nx}x{case.ny} lattice (same initial state), FP64 reference, {n} steps after 2 untimed, "
                   f"{dt:.1f} s",
+        "single_core": cpu_baseline_one_core(),
     }
+
+
+_ONE_CORE = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1501_05430_amd import workloads as W
+case = W.c1_neutral()
+sim = oracle.Sim(case.nx, case.ny, case.T_over_Tc, theta_bottom=case.theta_bottom, theta_top=case.theta_top)
+sim.init_droplets(case.xc, case.yc, case.R)
+sim.run(5)
+t0 = time.perf_counter()
+n = 0
+while time.perf_counter() - t0 < 5.0:
+    sim.run(50)
+    n += 50
+dt = time.perf_counter() - t0
+print(json.dumps({"value": round(case.fluid_nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
+                  "sample": f"{case.nx}x{case.ny} lattice, {n} steps, {dt:.1f} s"}))
+"""
+
+
+def cpu_baseline_one_core():
+    """The reference on one core (a child process with OMP_NUM_THREADS=1), on the small 200 x 100 lattice."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", _ONE_CORE, ROOT], env=env, capture_output=True, text=True,
+                             timeout=120, check=True).stdout
+        return json.loads(out.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        return {"error": str(e)[:200]}
 
 
 def batched_vs_plain(steps_batched=1000, steps_plain=200):
