@@ -53,6 +53,12 @@ typedef enum {
   LBM_F32_SHIFTED = 2  /* FP32 storage of f_i - w_i rho0 (rho0 = rho0_shift), computed in FP32 */
 } lbm_precision;
 
+typedef enum {
+  LBM_WALLS_Y = 0,     /* rows 0 and ny-1 are the walls' ghost rows (Sec. 4 wetting, halfway bounce-back) */
+  LBM_PERIODIC_Y = 1   /* no walls: fluid rows 1..ny-2 wrap around (a periodic lattice of ny-2 rows; the ghost
+                          rows are unused and read back as 0). x is periodic in both cases. Forward only. */
+} lbm_boundary;
+
 typedef struct lbm_ctx lbm_ctx; /* opaque; holds host memory only */
 
 /* Parameters of one lattice instance. Defaults in brackets are the paper's / the workloads' values. */
@@ -67,6 +73,8 @@ typedef struct {
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects 1, 2, 4 or 8 wavefronts (64, 128, 256 or 512
                              aligned columns) per block; 0 = library default. Instance 0's value applies to the
                              whole context (lbm_autotune may change it). Results do not depend on it (bitwise). */
+  int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y]; LBM_PERIODIC_Y excludes enable_adjoint */
+  int32_t reserved;       /* must be 0 */
   double tau;             /* BGK relaxation time (> 0.5) [1.0] */
   double G;               /* interaction strength, < 0 [-1.0] */
   double A;               /* hybrid-force parameter of Eq. 9 [-0.6]; 0 = plain Shan-Chen force (Eq. 7) */

@@ -178,16 +178,18 @@ __device__ inline double ghost_density(double rL, double rR, double r1, double r
 }
 
 // Streamed populations at fluid node (x, y) (rows 1..ny-2) from the stored post-collision ones (see the file
-// header): f_i(x) = g_i(x - e_i), or g_{opp(i)}(x) where x - e_i is a ghost row (halfway bounce-back).
+// header): f_i(x) = g_i(x - e_i), or g_{opp(i)}(x) where x - e_i is a ghost row (halfway bounce-back). With
+// periodic rows (py) the rows below row 1 and above row ny-2 are rows ny-2 and 1.
 template <class S, class C>
 __device__ inline void gather(const typename Gbl<S>::T* __restrict__ g, int64_t plane, int pitch, int nx, int ny,
-                              int x, int y, C (&f)[9]) {
+                              int x, int y, C (&f)[9], bool py = false) {
   typedef typename Gbl<S>::T GS;
   const int xl = x == 0 ? nx - 1 : x - 1, xr = x + 1 == nx ? 0 : x + 1;
-  const bool bot = (y == 1), top = (y == ny - 2);
+  const bool bot = !py && (y == 1), top = !py && (y == ny - 2);
   const unsigned rc = (unsigned)((y - 1) * pitch);
-  const unsigned rd = bot ? rc : rc - (unsigned)pitch;  // row below (unused at the bottom wall)
-  const unsigned ru = top ? rc : rc + (unsigned)pitch;  // row above (unused at the top wall)
+  // row below (unused at the bottom wall) and row above (unused at the top wall)
+  const unsigned rd = bot ? rc : (y == 1 ? (unsigned)((ny - 3) * pitch) : rc - (unsigned)pitch);
+  const unsigned ru = top ? rc : (y == ny - 2 ? 0u : rc + (unsigned)pitch);
   auto P = [&](int q, unsigned off) -> C { return (C)((const GS*)(g + q * plane))[off]; };
   f[0] = P(0, rc + x);
   f[1] = P(1, rc + xl);

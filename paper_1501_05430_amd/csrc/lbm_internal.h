@@ -15,7 +15,7 @@ struct InstDesc {
   int32_t nx, ny, pitch, wet_iters;
   int64_t plane;            // (ny-2) * pitch elements per population
   int32_t cur;              // buffer holding the state before a launch with flip s = 0
-  int32_t pad0;
+  int32_t periodic_y;       // 1: fluid rows 1..ny-2 wrap around, no walls (LBM_PERIODIC_Y)
   double RT;                // R * T
   double eos_a, eos_b4;     // a, b/4
   double two_over_Gpsi;     // 2 / G (G inside psi, Eq. 10)

@@ -50,6 +50,8 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   const int x0 = uni(t.x0), y0 = uni(t.y0), bw = uni(t.wh & 0xffff), nrows = uni(t.wh >> 16);
   const int ylast = y0 + nrows - 1;
   const C rho0 = (C)d.rho0;
+  const bool py = d.periodic_y != 0;  // rows wrap around, no walls
+  auto wrapy = [&](int y) { return y < 1 ? y + (ny - 2) : (y > ny - 2 ? y - (ny - 2) : y); };
 
   const int lx = wv * WAVE + lane;  // column offset inside the block
   const bool act = lx < bw;
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   // Row y (fluid): own column populations, density and psi; edge lanes also density and psi of the halo column.
   auto produce = [&](int y, C (&f)[9], C& rho, C& psi, C& hrho, C& hpsi, bool& cl) {
     if (act) {
-      gather<S, C>(gin, plane, pitch, nx, ny, col, y, f);
+      gather<S, C>(gin, plane, pitch, nx, ny, col, wrapy(y), f, py);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = (C)0;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
     hpsi = (C)0;
     if (edge) {
       C g[9];
-      gather<S, C>(gin, plane, pitch, nx, ny, hcol, y, g);
+      gather<S, C>(gin, plane, pitch, nx, ny, hcol, wrapy(y), g, py);
       hrho = rho0 + sum9(g);
       bool dm;
       hpsi = psi_eval(d, hrho, dm);
@@ -145,9 +147,9 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   // below (y - 1) and above (y + 1).
   constexpr int st = DOWN ? -1 : 1;
   const int ystart = DOWN ? ylast : y0, yend = DOWN ? y0 : ylast;
-  auto fluid_row = [&](int y) { return y >= 1 && y <= ny - 2; };
-  const bool wall_start = DOWN ? (ylast == ny - 2) : (y0 == 1);  // a wall behind the first row of the walk
-  const bool wall_end = DOWN ? (y0 == 1) : (ylast == ny - 2);     // a wall ahead of the last row of the walk
+  auto fluid_row = [&](int y) { return py || (y >= 1 && y <= ny - 2); };
+  const bool wall_start = !py && (DOWN ? (ylast == ny - 2) : (y0 == 1));  // a wall behind the walk's first row
+  const bool wall_end = !py && (DOWN ? (y0 == 1) : (ylast == ny - 2));     // a wall ahead of the walk's last row
 
   // The far wall: its ghost row's psi (with its neighbours) is computed up front, so that the row loop itself
   // carries no wall code.
@@ -188,11 +190,15 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
       cl_a = false;
     }
   }
-  // rows read by the strip: ystart - st .. yend + st, clipped to the fluid rows; with PF the populations of row
-  // y + 2 st are in flight while row y is processed
+  // rows read by the strip: ystart - st .. yend + st, clipped to the fluid rows (wrapped when periodic); with PF
+  // the populations of row y + 2 st are in flight while row y is processed
   const int yread = DOWN ? (y0 - 1 >= 1 ? y0 - 1 : 1) : (ylast + 1 <= ny - 2 ? ylast + 1 : ny - 2);
-  auto readable = [&](int y) { return DOWN ? y >= yread : y <= yread; };
-  if (PF && act && readable(ystart + 2 * st)) gather<S, C>(gin, plane, pitch, nx, ny, col, ystart + 2 * st, fp);
+  auto readable = [&](int y) {
+    if (py) return (y - ystart) * st <= (yend - ystart) * st + 1;
+    return DOWN ? y >= yread : y <= yread;
+  };
+  if (PF && act && readable(ystart + 2 * st))
+    gather<S, C>(gin, plane, pitch, nx, ny, col, wrapy(ystart + 2 * st), fp, py);
 
   for (int y = ystart;; y += st) {
     if (act) {
@@ -241,11 +247,11 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
       if (PF) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) fn[i] = act ? fp[i] : (C)0;
-        if (act && readable(ynew + st)) gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + st, fp);
-        if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
+        if (act && readable(ynew + st)) gather<S, C>(gin, plane, pitch, nx, ny, col, wrapy(ynew + st), fp, py);
+        if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, wrapy(ynew), g, py);
       } else if (act) {
-        gather<S, C>(gin, plane, pitch, nx, ny, col, ynew, fn);
-        if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
+        gather<S, C>(gin, plane, pitch, nx, ny, col, wrapy(ynew), fn, py);
+        if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, wrapy(ynew), g, py);
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) fn[i] = (C)0;
@@ -350,7 +356,8 @@ __global__ __launch_bounds__(BLOCK) void k_init_rho(const InstDesc* __restrict__
   for (int j = 0; j < ndrops; ++j) {
     double dx = (double)x - drops[3 * j];
     dx -= (double)nx * floor(dx / (double)nx + 0.5);
-    const double dy = (double)y - drops[3 * j + 1];
+    double dy = (double)y - drops[3 * j + 1];
+    if (d.periodic_y) dy -= (double)nyf * floor(dy / (double)nyf + 0.5);  // nearest periodic image
     const double dist = sqrt(dx * dx + dy * dy);
     const double v = rho_v + (rho_l - rho_v) * 0.5 * (1.0 - tanh(2.0 * (dist - drops[3 * j + 2]) / width));
     if (v > r) r = v;
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(BLOCK) void k_init_rho(const InstDesc* __restrict__
 
 
 // Rest state f_i = w_i rho stored as post-collision populations: g_i(x) = f_i(x + e_i), or f_{opp(i)}(x) where
-// x + e_i is a ghost row (the inverse of the gather).
+// x + e_i is a ghost row (the inverse of the gather; with periodic rows x + e_i wraps instead).
 template <class S>
 __global__ __launch_bounds__(BLOCK) void k_init_pops(const InstDesc* __restrict__ descs, int inst,
                                                      const double* __restrict__ rho) {
@@ -374,8 +381,13 @@ __global__ __launch_bounds__(BLOCK) void k_init_pops(const InstDesc* __restrict_
   const int64_t idx = (int64_t)(y - 1) * d.pitch + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const int yd = y + kEY[i];
-    const double r = (yd < 1 || yd > ny - 2) ? rho[(int64_t)y * nx + x] : rho[(int64_t)yd * nx + wrapx(x + kEX[i], nx)];
+    int yd = y + kEY[i];
+    bool wall = yd < 1 || yd > ny - 2;
+    if (wall && d.periodic_y) {
+      yd = yd < 1 ? ny - 2 : 1;
+      wall = false;
+    }
+    const double r = wall ? rho[(int64_t)y * nx + x] : rho[(int64_t)yd * nx + wrapx(x + kEX[i], nx)];
     g[i * d.plane + idx] = (S)(kW[i] * r - kW[i] * d.rho0);
   }
 }
@@ -390,6 +402,10 @@ __global__ __launch_bounds__(BLOCK) void k_wetting(const InstDesc* __restrict__ 
   const int t = (int)(blockIdx.x * BLOCK + threadIdx.x);
   if (t >= 2 * nx) return;
   const int wall = t / nx, x = t % nx;
+  if (d.periodic_y) {  // no walls
+    d.ghost[wall * nx + x] = 0.0;
+    return;
+  }
   const typename Gbl<S>::T* g = (const typename Gbl<S>::T*)d.f[d.cur];
   const C rho0 = (C)d.rho0;
   const int r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
@@ -418,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_get_rho(const InstDesc* __restrict__ 
   if (y == 0) { dst[k] = d.ghost[x]; return; }
   if (y == ny - 1) { dst[k] = d.ghost[nx + x]; return; }
   double f[9];
-  gather<S, double>((const typename Gbl<S>::T*)d.f[d.cur], d.plane, d.pitch, nx, ny, x, y, f);
+  gather<S, double>((const typename Gbl<S>::T*)d.f[d.cur], d.plane, d.pitch, nx, ny, x, y, f, d.periodic_y != 0);
   dst[k] = sum9(f) + d.rho0;
 }
 
@@ -433,7 +449,7 @@ __global__ __launch_bounds__(BLOCK) void k_get_pops(const InstDesc* __restrict__
   if (k >= n) return;
   const int x = (int)(k % nx), y = (int)(k / nx) + 1;
   double f[9];
-  gather<S, double>((const typename Gbl<S>::T*)d.f[d.cur], d.plane, d.pitch, nx, ny, x, y, f);
+  gather<S, double>((const typename Gbl<S>::T*)d.f[d.cur], d.plane, d.pitch, nx, ny, x, y, f, d.periodic_y != 0);
   for (int i = q0; i < q1; ++i) dst[(i - q0) * n + k] = f[i] + kW[i] * d.rho0;
 }
 
@@ -448,8 +464,12 @@ __global__ __launch_bounds__(BLOCK) void k_set_plane(const InstDesc* __restrict_
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (k >= (int64_t)nx * (ny - 2)) return;
   const int x = (int)(k % nx), y = (int)(k / nx) + 1;
-  const int yd = y + kEY[q];
-  const bool wall = yd < 1 || yd > ny - 2;
+  int yd = y + kEY[q];
+  bool wall = yd < 1 || yd > ny - 2;
+  if (wall && d.periodic_y) {
+    yd = yd < 1 ? ny - 2 : 1;
+    wall = false;
+  }
   S* g = (S*)d.f[d.cur];
   const int64_t idx = (int64_t)q * d.plane + (int64_t)(y - 1) * d.pitch + x;
   if (p == q && !wall) g[idx] = (S)(src[(int64_t)(yd - 1) * nx + wrapx(x + kEX[q], nx)] - kW[q] * d.rho0);

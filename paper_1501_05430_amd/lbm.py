@@ -9,11 +9,16 @@ from . import _lib
 from ._lib import LbmError, Params, check, PRECISIONS
 
 
+BOUNDARIES = {"walls": 0, "periodic": 1}
+
+
 def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=0, strip_rows=0,
                 enable_adjoint=False, step_variant=0, tau=1.0, G=-1.0, A=-0.6, eos_a=1.0, eos_b=4.0, eos_R=1.0, rho0_shift=0.0,
-                rho_fp64_below=0.0, body_force=(0.0, 0.0)):
-    """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'."""
+                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls"):
+    """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'; boundary: 'walls'
+    (ghost rows 0 and ny-1 with the geometric wetting) or 'periodic' (fluid rows 1..ny-2 wrap around)."""
     p = Params()
+    p.boundary = BOUNDARIES[boundary] if isinstance(boundary, str) else int(boundary)
     p.nx, p.ny = int(nx), int(ny)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.wet_iters = int(wet_iters)

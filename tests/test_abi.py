@@ -35,9 +35,9 @@ def test_binding_declares_every_entry_point():
 
 
 def test_params_struct_matches_header_size():
-    # lbm_params: 8 int32 + 11 double = 120 bytes, no padding
+    # lbm_params: 10 int32 + 11 double = 128 bytes, no padding
     from paper_1501_05430_amd import _lib
-    assert C.sizeof(_lib.Params) == 8 * 4 + 11 * 8
+    assert C.sizeof(_lib.Params) == 10 * 4 + 11 * 8
 
 
 def test_workspace_bytes_and_validation():
@@ -57,6 +57,8 @@ def test_workspace_bytes_and_validation():
         dict(nx=20, ny=10, T_over_Tc=0.8, wet_iters=-1),
         dict(nx=20, ny=10, T_over_Tc=0.8, step_variant=9),
         dict(nx=20, ny=10, T_over_Tc=0.8, rho0_shift=0.3),
+        dict(nx=20, ny=10, T_over_Tc=0.8, boundary=2),
+        dict(nx=20, ny=10, T_over_Tc=0.8, boundary="periodic", enable_adjoint=True),
     ]
     for kw in bad:
         with pytest.raises(P.LbmError):
