@@ -1,0 +1,99 @@
+"""Edge cases through the C-ABI: an empty lattice (no droplet), the smallest lattices, the largest lattice the
+32-bit offsets allow (checked through properties that hold at any size), and calls out of order."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import oracle_pops
+
+pytestmark = pytest.mark.gpu
+
+
+def test_no_droplet_matches_reference_and_stays_uniform(ora):
+    import paper_1501_05430_amd as P
+    nx, ny = 96, 40
+    th = np.radians(np.linspace(30.0, 150.0, nx))
+    ref = ora.Sim(nx, ny, 0.7, theta_bottom=th, theta_top=th[::-1].copy())
+    ref.init_droplets([], [], [])
+    sim = P.LBM(P.make_params(nx, ny, 0.7))
+    sim.apply_wetting(th, th[::-1].copy())
+    sim.init_droplet([], [], [])
+    ref.run(200)
+    sim.step(200)
+    rv, _ = ref.coexistence()
+    r = sim.rho()[1:-1]
+    assert np.abs(sim.populations() - oracle_pops(ref)).max() <= 1e-12 * rv
+    assert np.abs(r - rv).max() <= 1e-12 * rv   # a uniform vapour: no interface, no force, no flow
+    sim.close()
+
+
+@pytest.mark.parametrize("nx,ny,steps,drop", [
+    (2, 4, 60, (1.0, 0.5, 1.5)),
+    (3, 5, 60, (1.5, 0.5, 2.0)),
+    (65, 4, 60, (32.0, 0.5, 6.0)),
+    (129, 7, 60, (64.0, 0.5, 20.0)),
+])
+def test_smallest_lattices_match_reference(ora, nx, ny, steps, drop):
+    import paper_1501_05430_amd as P
+    th = np.full(nx, math.radians(70.0))
+    ref = ora.Sim(nx, ny, 0.8, theta_bottom=th, theta_top=th)
+    ref.init_droplets([drop[0]], [drop[1]], [drop[2]])
+    sim = P.LBM(P.make_params(nx, ny, 0.8))
+    sim.apply_wetting(th, th)
+    sim.init_droplet(drop[0], drop[1], drop[2])
+    ref.run(steps)
+    sim.step(steps)
+    f_ref = oracle_pops(ref)
+    err = np.abs(sim.populations() - f_ref).max() / np.abs(f_ref).max()
+    sim.close()
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("precision", ["f32_shifted", "f64"])
+def test_largest_lattice(precision):
+    """16384 columns x 14563 fluid rows (9 * pitch * rows just below 2^31): 20 steps with a droplet centred at
+    x = nx/2 run without a fault or a non-finite value, conserve mass and stay mirror-symmetric bit for bit."""
+    import torch
+    import paper_1501_05430_amd as P
+    nx = 16384
+    nyf = (2 ** 31 - 1) // (9 * nx)
+    kw = P.fp32_options(0.7, precision)
+    with pytest.raises(P.LbmError):   # one more row exceeds the offsets
+        P.workspace_bytes(P.make_params(nx, nyf + 3, 0.7, precision=precision, **kw))
+    sim = P.LBM(P.make_params(nx, nyf + 2, 0.7, precision=precision, check_every=10, **kw))
+    sim.apply_wetting(math.radians(60.0), math.radians(90.0))
+    sim.init_droplet([nx / 2, nx / 2], [0.5 - 3000 * math.cos(math.radians(60.0)), 9000.0], [3000.0, 1500.0])
+    m0 = sim.mass()
+    sim.step(20)
+    d = sim.diag()
+    m1 = sim.mass()
+    r = sim.rho(device=True)[1:-1]
+    mirror = torch.remainder(-torch.arange(nx, device=r.device), nx)
+    symmetric = bool(torch.equal(r, r.index_select(1, mirror)))
+    finite = bool(torch.isfinite(r).all())
+    del r
+    sim.close()
+    assert d["nonfinite"] == 0 and finite
+    assert abs(m1 - m0) / m0 <= (1e-12 if precision == "f64" else 1e-6)
+    assert symmetric
+
+
+def test_calls_out_of_order_are_errors():
+    import paper_1501_05430_amd as P
+    sim = P.LBM(P.make_params(20, 10, 0.8))
+    with pytest.raises(P.LbmError) as e:
+        sim.step(1)                      # no state yet
+    assert e.value.code == 5
+    with pytest.raises(P.LbmError) as e:
+        sim.step(1, inst=1)              # no such instance
+    assert e.value.code == 1
+    sim.init_droplet(10.0, 0.5, 4.0)
+    sim.step(0)                          # a no-op
+    import ctypes as C
+    buf = C.c_void_p(sim._ws_ptr)        # any device address: the call must refuse before using it
+    rc = sim.lib.lbm_adjoint_step(sim.ctx, 0, buf, buf, buf, buf, buf)
+    assert rc == 5                       # created without enable_adjoint
+    rc = sim.lib.lbm_adjoint_step(sim.ctx, 0, None, buf, buf, buf, buf)
+    assert rc == 1                       # NULL buffer
+    sim.close()
