@@ -16,7 +16,8 @@
 //    Guo forcing; tau is kept general (BGK), with v = (j + F/2)/rho.
 //  * Force: Eq. (9) (Kupershtokh hybrid, parameter A) with the weights of Eq. (7), w(1)=1/3, w(2)=1/12, and
 //    U = G psi^2 / 2 (Eq. 8). A = 0 is the plain Shan-Chen force of Eq. (7).
-//  * psi from Eq. (10) with c = 1: psi = sqrt(2 (p_EOS(rho) - rho/3) / G); p_EOS is Carnahan-Starling.
+//  * psi from Eq. (10) with c = 1: psi = sqrt(2 (p_EOS(rho) - rho/3) / G); p_EOS is Carnahan-Starling, or the
+//    piecewise-linear EOS of Eq. (11) with break points from Eq. (12)-(13).
 //  * Wall: rows 0 and ny-1 are the ghost layer (index 0 of Sec. 4), rows 1 and ny-2 the boundary nodes (index 1),
 //    rows 2 and ny-3 index 2. Ghost rows carry density and psi only. Populations use halfway bounce-back.
 //  * Ghost density: Eq. (19) when wet_iters == 0; otherwise the iteration of Eq. (21) with the square root of
@@ -74,6 +75,10 @@ typedef struct {
   double eos_a, eos_b, eos_R;
   double T;              // absolute temperature of the Carnahan-Starling EOS
   double body_fx, body_fy;  // constant body force F_g of Eq. (7), per unit volume
+  int32_t eos_kind;      // 0: Carnahan-Starling (eos_a, eos_b, eos_R, T); 1: piecewise-linear EOS of Eq. (11)
+  int32_t pad;
+  double pw_theta_v, pw_theta_m, pw_theta_l;  // Eq. (11): slopes of the vapour, unstable and liquid branches
+  double pw_rho1, pw_rho2;                    // Eq. (11): break points (from Eq. 12-13, ora_pw_breakpoints)
 } ora_params;
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -224,6 +229,54 @@ double ora_cs_rho_cap(double a, double b, double R, double T, double G) {
   return lo;
 }
 
+// ---------------------------------------------------------------------------------------------------------------
+// Piecewise-linear EOS of Eq. (11) (the self-tuning EOS the paper adopts): slope theta_v up to rho_1, theta_m
+// between rho_1 and rho_2, theta_l above rho_2, continuous, p(0) = 0.
+// ---------------------------------------------------------------------------------------------------------------
+double ora_pw_pressure(double tv, double tm, double tl, double r1, double r2, double rho) {
+  if (rho <= r1) return rho * tv;
+  if (rho <= r2) return r1 * tv + (rho - r1) * tm;
+  return r1 * tv + (r2 - r1) * tm + (rho - r2) * tl;
+}
+
+// Break points rho_1 < rho_2 for given coexistence densities rho_v < rho_l and slopes: Eq. (12) (equal pressure,
+// the integral of dp) and Eq. (13) (equal chemical potential, the integral of dp / rho) written out. Eq. (12) gives
+// rho_2 as a linear function of rho_1; Eq. (13) is then one equation in rho_1, solved by bisection over the rho_1
+// for which rho_v <= rho_1 < rho_2 <= rho_l. Returns 0 on success.
+int ora_pw_breakpoints(double tv, double tm, double tl, double rv, double rl, double* r1, double* r2) {
+  if (!(rv > 0 && rl > rv && tv > 0 && tl > 0 && tm < 0)) return 1;
+  auto rho2_of = [&](double x) { return (rv * tv - x * tv + x * tm - rl * tl) / (tm - tl); };  // Eq. (12)
+  auto eq13 = [&](double x) {
+    const double y = rho2_of(x);
+    return std::log(x / rv) * tv + std::log(y / x) * tm + std::log(rl / y) * tl;
+  };
+  // feasible rho_1: rho_1 >= rho_v and rho_2(rho_1) in (rho_1, rho_l]
+  double lo = rv, hi = rl;
+  for (int it = 0; it < 200; ++it) {  // shrink hi until rho_2(hi) > hi
+    if (rho2_of(hi) > hi && rho2_of(hi) <= rl) break;
+    hi = lo + 0.5 * (hi - lo);
+  }
+  double flo = eq13(lo), fhi = eq13(hi);
+  if (!std::isfinite(flo) || !std::isfinite(fhi) || (flo < 0) == (fhi < 0)) return 2;
+  for (int it = 0; it < 300; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    const double fm = eq13(mid);
+    if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else { hi = mid; }
+  }
+  *r1 = 0.5 * (lo + hi);
+  *r2 = rho2_of(*r1);
+  return 0;
+}
+
+// Largest density with real psi for the piecewise EOS: the root of p(rho) = rho/3 on the liquid branch when its
+// slope exceeds 1/3, else unbounded.
+double ora_pw_rho_cap(double tv, double tm, double tl, double r1, double r2) {
+  const double h2 = ora_pw_pressure(tv, tm, tl, r1, r2, r2) - r2 / 3.0;
+  if (tl > 1.0 / 3.0) return r2 - h2 / (tl - 1.0 / 3.0);
+  return 1e300;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -238,6 +291,12 @@ struct Counters {
 
 template <class S>
 S cs_pressure_t(const ora_params& p, const S& rho) {
+  if (p.eos_kind == 1) {  // Eq. (11); the branch follows the real part
+    const double r = re(rho);
+    if (r <= p.pw_rho1) return rho * p.pw_theta_v;
+    if (r <= p.pw_rho2) return p.pw_rho1 * p.pw_theta_v + (rho - p.pw_rho1) * p.pw_theta_m;
+    return p.pw_rho1 * p.pw_theta_v + (p.pw_rho2 - p.pw_rho1) * p.pw_theta_m + (rho - p.pw_rho2) * p.pw_theta_l;
+  }
   S eta = p.eos_b * rho / 4.0;
   S num = 1.0 + eta + eta * eta - eta * eta * eta;
   S om = 1.0 - eta;
@@ -285,7 +344,8 @@ struct Oracle {
   std::vector<S> rho, jx, jy, psi;
 
   Oracle(const ora_params& pp, S gf, S gpsi) : p(pp), G_f(gf), G_psi(gpsi), nx(pp.nx), ny(pp.ny) {
-    rho_cap = ora_cs_rho_cap(p.eos_a, p.eos_b, p.eos_R, p.T, re(G_psi));
+    rho_cap = p.eos_kind == 1 ? ora_pw_rho_cap(p.pw_theta_v, p.pw_theta_m, p.pw_theta_l, p.pw_rho1, p.pw_rho2)
+                              : ora_cs_rho_cap(p.eos_a, p.eos_b, p.eos_R, p.T, re(G_psi));
     rho.assign((size_t)nx * ny, S(0.0));
     jx.assign((size_t)nx * ny, S(0.0));
     jy.assign((size_t)nx * ny, S(0.0));
@@ -417,8 +477,10 @@ void run_steps(const ora_params& p, S G_f, S G_psi, S* f, int64_t nsteps, const 
 
 bool params_ok(const ora_params* p) {
   if (!p || p->nx < 1 || p->ny < (p->periodic_y ? 1 : 4) || p->wet_iters < 0) return false;
-  if (!(p->tau > 0.5) || !(p->G < 0) || !(p->T > 0)) return false;
-  return true;
+  if (!(p->tau > 0.5) || !(p->G < 0)) return false;
+  if (p->eos_kind == 1)
+    return p->pw_theta_v > 0 && p->pw_theta_m < 0 && p->pw_theta_l > 0 && p->pw_rho1 > 0 && p->pw_rho2 > p->pw_rho1;
+  return p->eos_kind == 0 && p->T > 0;
 }
 
 }  // namespace

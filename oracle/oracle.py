@@ -19,6 +19,9 @@ class OraParams(C.Structure):
         ("tau", C.c_double), ("G", C.c_double), ("A", C.c_double),
         ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("T", C.c_double),
         ("body_fx", C.c_double), ("body_fy", C.c_double),
+        ("eos_kind", C.c_int32), ("pad", C.c_int32),
+        ("pw_theta_v", C.c_double), ("pw_theta_m", C.c_double), ("pw_theta_l", C.c_double),
+        ("pw_rho1", C.c_double), ("pw_rho2", C.c_double),
     ]
 
 
@@ -48,6 +51,9 @@ def lib():
         L.ora_init_droplets.argtypes = [pp, p, i32, p, p, p, d, d, d]; L.ora_init_droplets.restype = C.c_int
         L.ora_mass.argtypes = [pp, p]; L.ora_mass.restype = d
         L.ora_num_threads.argtypes = []; L.ora_num_threads.restype = i32
+        L.ora_pw_pressure.argtypes = [d, d, d, d, d, d]; L.ora_pw_pressure.restype = d
+        L.ora_pw_breakpoints.argtypes = [d, d, d, d, d, p, p]; L.ora_pw_breakpoints.restype = C.c_int
+        L.ora_pw_rho_cap.argtypes = [d, d, d, d, d]; L.ora_pw_rho_cap.restype = d
         _lib = L
     return _lib
 
@@ -95,6 +101,23 @@ def cs_rho_cap(T, G=-1.0, a=1.0, b=4.0, R=1.0):
     return lib().ora_cs_rho_cap(a, b, R, T, G)
 
 
+def pw_breakpoints(theta_v, theta_m, theta_l, rho_v, rho_l):
+    """(rho_1, rho_2) of the piecewise-linear EOS (Eq. 11) from Eq. (12)-(13)."""
+    r1, r2 = C.c_double(), C.c_double()
+    rc_ = lib().ora_pw_breakpoints(theta_v, theta_m, theta_l, rho_v, rho_l, C.byref(r1), C.byref(r2))
+    if rc_:
+        raise ValueError(f"no break points ({rc_})")
+    return r1.value, r2.value
+
+
+def pw_pressure(theta_v, theta_m, theta_l, rho1, rho2, rho):
+    return lib().ora_pw_pressure(theta_v, theta_m, theta_l, rho1, rho2, float(rho))
+
+
+def pw_rho_cap(theta_v, theta_m, theta_l, rho1, rho2):
+    return lib().ora_pw_rho_cap(theta_v, theta_m, theta_l, rho1, rho2)
+
+
 def ghost_density(r_im1_1, r_ip1_1, r_i_1, r_i_2, theta, iters):
     return lib().ora_ghost_density(float(r_im1_1), float(r_ip1_1), float(r_i_1), float(r_i_2), float(theta),
                                    int(iters))
@@ -105,12 +128,24 @@ class Sim:
     """One lattice (state in self.f, [ny, nx, 9] float64) advanced by the reference step."""
 
     def __init__(self, nx, ny, T_over_Tc, theta_bottom=np.pi / 2, theta_top=np.pi / 2, *, wet_iters=4, tau=1.0,
-                 G=-1.0, A=-0.6, a=1.0, b=4.0, R=1.0, body_force=(0.0, 0.0), periodic_y=False):
-        rc, tc, pc = cs_critical(a, b, R)
-        self.T_c = tc
-        self.T = T_over_Tc * tc
+                 G=-1.0, A=-0.6, a=1.0, b=4.0, R=1.0, body_force=(0.0, 0.0), periodic_y=False, piecewise=None):
+        """piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the EOS of Eq. (11) with the break points
+        of Eq. (12)-(13) (T_over_Tc is then unused); None selects Carnahan-Starling."""
+        if piecewise is None:
+            rc, tc, pc = cs_critical(a, b, R)
+            self.T_c = tc
+            self.T = T_over_Tc * tc
+        else:
+            self.T_c = self.T = 1.0
         self.p = OraParams(nx, ny, 1 if periodic_y else 0, wet_iters, tau, G, A, a, b, R, self.T,
                            body_force[0], body_force[1])
+        self.piecewise = piecewise
+        if piecewise is not None:
+            tv, tm, tl, rv, rl = piecewise
+            r1, r2 = pw_breakpoints(tv, tm, tl, rv, rl)
+            self.p.eos_kind = 1
+            self.p.pw_theta_v, self.p.pw_theta_m, self.p.pw_theta_l = tv, tm, tl
+            self.p.pw_rho1, self.p.pw_rho2 = r1, r2
         self.nx, self.ny = nx, ny
         self.f = np.zeros((ny, nx, 9), dtype=np.float64)
         self.theta_b = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_bottom, np.float64), (nx,)))
@@ -119,6 +154,8 @@ class Sim:
         self.steps = 0
 
     def coexistence(self):
+        if self.piecewise is not None:  # the densities Eq. (12)-(13) were solved for
+            return self.piecewise[3], self.piecewise[4]
         return cs_maxwell(self.T, self.p.eos_a, self.p.eos_b, self.p.eos_R)
 
     def init_droplets(self, xc, yc, R, width=5.0, rho_l=None, rho_v=None):
@@ -194,4 +231,5 @@ def psi(sim, rho):
 
 
 __all__ = ["OraParams", "lib", "cs_pressure", "cs_dpdrho", "cs_d2pdrho2", "cs_mu", "cs_critical", "cs_maxwell",
-           "cs_rho_cap", "ghost_density", "Sim", "collide_node", "psi", "num_threads"]
+           "cs_rho_cap", "pw_breakpoints", "pw_pressure", "pw_rho_cap", "ghost_density", "Sim", "collide_node", "psi",
+           "num_threads"]

@@ -1,4 +1,6 @@
 """Pins of the reference's Carnahan-Starling EOS, coexistence and psi (Eq. 10), independent of its own code."""
+import os
+
 import numpy as np
 import pytest
 from scipy import integrate
@@ -85,3 +87,83 @@ def test_psi_eq10_and_cap(ora, t):
         assert s * s == pytest.approx(2 * (rho / 3 - ora.cs_pressure(rho, sim.T)), rel=1e-12)
         assert s > 0
     assert ora.psi(sim, cap * 1.01) == 0.0  # clamped
+
+
+# ------------------------------------------------------------------------------------------------ Eq. (11)-(13)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pw_eos_table1.txt")
+
+
+def table1():
+    rows = []
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            ratio, r1, r2, tv, tm, tl = (float(v) for v in line.split())
+            rows.append(dict(ratio=ratio, rho1=r1, rho2=r2, tv=tv, tm=tm, tl=tl))
+    return rows
+
+
+@pytest.mark.parametrize("row", table1(), ids=lambda r: f"ratio{r['ratio']:g}")
+def test_pw_breakpoints_reproduce_table1(ora, row):
+    r1, r2 = ora.pw_breakpoints(row["tv"], row["tm"], row["tl"], 1.0, row["ratio"])
+    # the printed rho_1 carry 4 significant digits and rho_2 4 to 7; the paper's own rounding reaches 4.2e-4
+    assert abs(r1 - row["rho1"]) <= 1e-3 * row["rho1"]
+    assert abs(r2 - row["rho2"]) <= 1e-4 * row["rho2"]
+
+
+@pytest.mark.parametrize("row", table1(), ids=lambda r: f"ratio{r['ratio']:g}")
+def test_pw_printed_breakpoints_nearly_solve_eq12_13(row):
+    # independent of the solver: the printed values must be near-roots of the two balances as written in the paper
+    rv, rl, r1, r2, tv, tm, tl = 1.0, row["ratio"], row["rho1"], row["rho2"], row["tv"], row["tm"], row["tl"]
+    t12 = [(r1 - rv) * tv, (r2 - r1) * tm, (rl - r2) * tl]
+    t13 = [np.log(r1 / rv) * tv, np.log(r2 / r1) * tm, np.log(rl / r2) * tl]
+    assert abs(sum(t12)) <= 2e-3 * sum(abs(t) for t in t12)
+    assert abs(sum(t13)) <= 2e-3 * sum(abs(t) for t in t13)
+
+
+@pytest.mark.parametrize("row", table1(), ids=lambda r: f"ratio{r['ratio']:g}")
+def test_pw_coexistence_by_quadrature(ora, row):
+    """Equal pressure at rho_v and rho_l, and equal chemical potential: the integral of dp / rho from rho_v to rho_l
+    vanishes, evaluated here by quadrature of the reference's p(rho) (not by the closed form of Eq. 13)."""
+    tv, tm, tl, rv, rl = row["tv"], row["tm"], row["tl"], 1.0, row["ratio"]
+    r1, r2 = ora.pw_breakpoints(tv, tm, tl, rv, rl)
+    p = lambda r: ora.pw_pressure(tv, tm, tl, r1, r2, r)
+    assert p(rl) == pytest.approx(p(rv), rel=1e-12, abs=1e-12)
+    dp = lambda r, h=1e-6: (p(r + h) - p(r - h)) / (2 * h)
+    pts = [rv, r1, r2, rl]
+    total = sum(integrate.quad(lambda r: dp(r) / r, a, b, epsabs=1e-13, epsrel=1e-12)[0]
+                for a, b in zip(pts[:-1], pts[1:]))
+    scale = tv * np.log(r1 / rv) + abs(tm) * np.log(r2 / r1) + tl * np.log(rl / r2)
+    assert abs(total) <= 1e-9 * scale
+    # continuity and slopes of Eq. (11)
+    for r, t_left, t_right in ((r1, tv, tm), (r2, tm, tl)):
+        assert p(r * (1 - 1e-9)) == pytest.approx(p(r), abs=1e-6)
+        assert (p(r) - p(r * (1 - 1e-6))) / (r * 1e-6) == pytest.approx(t_left, rel=1e-5)
+        assert (p(r * (1 + 1e-6)) - p(r)) / (r * 1e-6) == pytest.approx(t_right, rel=1e-5)
+
+
+def test_pw_rho_cap(ora):
+    # liquid slope below c_s^2 = 1/3: psi stays real above rho_2 (no cap)
+    r1, r2 = ora.pw_breakpoints(0.25, -0.02, 0.3, 1.0, 10.0)
+    assert ora.pw_rho_cap(0.25, -0.02, 0.3, r1, r2) > 1e100
+    # liquid slope above 1/3: p(rho) = rho/3 at the cap
+    cap = ora.pw_rho_cap(0.25, -0.02, 0.4, r1, r2)
+    assert cap > r2
+    assert ora.pw_pressure(0.25, -0.02, 0.4, r1, r2, cap) == pytest.approx(cap / 3.0, rel=1e-12)
+
+
+def test_pw_flat_interface_settles_at_eq12_13_densities(ora):
+    """A liquid slab in a periodic 4 x 120 box under the piecewise EOS (ratio 10 of Table 1) settles with bulk
+    densities within 1 % of the coexistence pair the break points were solved for: the step really uses Eq. (11)
+    (a Carnahan-Starling or mis-segmented pressure settles elsewhere). A = -0.3 brings the pseudo-potential's own
+    coexistence rule close to the equal-area one for this EOS."""
+    s = ora.Sim(4, 120, 1.0, periodic_y=True, piecewise=(0.25, -0.02, 0.3, 1.0, 10.0), A=-0.3)
+    rv, rl = s.coexistence()
+    y = np.arange(120)[:, None]
+    rho = np.where((y >= 30) & (y < 90), rl, rv) * np.ones((1, 4))
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    s.f[:] = rho[:, :, None] * w
+    s.run(6000)
+    r, _ = s.density()
+    assert abs(r[60, 0] - rl) <= 0.01 * rl
+    assert abs(r[0, 0] - rv) <= 0.01 * rv
+    assert s.mass() == pytest.approx(rho.sum(), rel=1e-12)
