@@ -250,12 +250,13 @@ int ora_pw_breakpoints(double tv, double tm, double tl, double rv, double rl, do
     const double y = rho2_of(x);
     return std::log(x / rv) * tv + std::log(y / x) * tm + std::log(rl / y) * tl;
   };
-  // feasible rho_1: rho_1 >= rho_v and rho_2(rho_1) in (rho_1, rho_l]
-  double lo = rv, hi = rl;
-  for (int it = 0; it < 200; ++it) {  // shrink hi until rho_2(hi) > hi
-    if (rho2_of(hi) > hi && rho2_of(hi) <= rl) break;
-    hi = lo + 0.5 * (hi - lo);
-  }
+  // feasible rho_1: the segment order of Eq. (11), rho_v <= rho_1 < rho_2(rho_1) <= rho_l. rho_2(rho_1) increases
+  // with rho_1 and reaches rho_l at rho_1 = (rv tv - rl tm) / (tv - tm); rho_2 - rho_1 is proportional to
+  // rho_1 (tv - tl) + rl tl - rv tv, which vanishes at (rl tl - rv tv) / (tl - tv).
+  double lo = rv, hi = (rv * tv - rl * tm) / (tv - tm);
+  if (tv > tl) lo = std::max(lo, (rl * tl - rv * tv) / (tl - tv));
+  if (tv < tl) hi = std::min(hi, (rl * tl - rv * tv) / (tl - tv));
+  if (!(lo < hi)) return 2;
   double flo = eq13(lo), fhi = eq13(hi);
   if (!std::isfinite(flo) || !std::isfinite(fhi) || (flo < 0) == (fhi < 0)) return 2;
   for (int it = 0; it < 300; ++it) {

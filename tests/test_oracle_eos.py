@@ -167,3 +167,31 @@ def test_pw_flat_interface_settles_at_eq12_13_densities(ora):
     assert abs(r[60, 0] - rl) <= 0.01 * rl
     assert abs(r[0, 0] - rv) <= 0.01 * rv
     assert s.mass() == pytest.approx(rho.sum(), rel=1e-12)
+
+
+def test_pw_breakpoints_found_wherever_a_root_exists(ora):
+    """Brute force over a grid of slopes and ratios: scan rho_1 across (rho_v, rho_l) with rho_2 from Eq. (12);
+    where Eq. (13) changes sign between feasible points (rho_1 < rho_2 < rho_l), the reference must return break
+    points in segment order satisfying both equations; whatever it returns must satisfy them."""
+    import itertools
+    found = 0
+    for tv, tm, tl, rl in itertools.product([0.05, 0.25, 0.33], [-0.001, -0.02, -0.5, -5.0], [0.01, 0.3, 1.0, 10.0],
+                                            [1.01, 2.0, 10.0, 1000.0]):
+        rv = 1.0
+        x = np.linspace(rv, rl, 20001)[1:-1]
+        y = (tv * (rv - x) + tm * x - tl * rl) / (tm - tl)                    # Eq. (12) solved for rho_2
+        ok = (x < y) & (y < rl)
+        h = tv * np.log(x / rv) + tm * np.log(np.where(ok, y, 1.0) / x) + tl * np.log(rl / np.where(ok, y, 1.0))
+        sign_change = bool(np.any(ok[:-1] & ok[1:] & (np.sign(h[:-1]) != np.sign(h[1:]))))
+        try:
+            r1, r2 = ora.pw_breakpoints(tv, tm, tl, rv, rl)
+        except ValueError:
+            assert not sign_change, (tv, tm, tl, rl)
+            continue
+        found += 1
+        assert rv < r1 < r2 < rl
+        e12 = (r1 - rv) * tv + (r2 - r1) * tm + (rl - r2) * tl
+        e13 = np.log(r1 / rv) * tv + np.log(r2 / r1) * tm + np.log(rl / r2) * tl
+        assert abs(e12) <= 1e-12 * rl * max(tv, abs(tm), tl)
+        assert abs(e13) <= 1e-12 * max(tv, abs(tm), tl) * np.log(rl / rv) + 1e-15
+    assert found > 100
