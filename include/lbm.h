@@ -59,6 +59,16 @@ typedef enum {
                           rows are unused and read back as 0). x is periodic in both cases. Forward only. */
 } lbm_boundary;
 
+typedef enum {
+  LBM_EOS_CARNAHAN_STARLING = 0,  /* p = rho R T (1 + e + e^2 - e^3) / (1 - e)^3 - a rho^2, e = b rho / 4, at
+                                     T = T_over_Tc T_c; coexistence from the equal-area construction */
+  LBM_EOS_PIECEWISE_LINEAR = 1    /* Eq. 11: slopes theta_v, theta_m, theta_l (pw_theta) on [0, rho_1],
+                                     [rho_1, rho_2], [rho_2, inf); the break points solve Eq. 12 (equal pressure)
+                                     and Eq. 13 (equal chemical potential) for the coexistence pair pw_rho. Needs
+                                     0 < theta_v < 1/3, theta_m < 0, theta_l > 0 and 0 < rho_v < rho_l, with psi
+                                     real up to rho_l; eos_a/b/R and T_over_Tc are ignored */
+} lbm_eos;
+
 typedef struct lbm_ctx lbm_ctx; /* opaque; holds host memory only */
 
 /* Parameters of one lattice instance. Defaults in brackets are the paper's / the workloads' values. */
@@ -74,7 +84,7 @@ typedef struct {
                              aligned columns) per block; 0 = library default. Instance 0's value applies to the
                              whole context (lbm_autotune may change it). Results do not depend on it (bitwise). */
   int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y]; LBM_PERIODIC_Y excludes enable_adjoint */
-  int32_t reserved;       /* must be 0 */
+  int32_t eos;            /* lbm_eos [LBM_EOS_CARNAHAN_STARLING] */
   double tau;             /* BGK relaxation time (> 0.5) [1.0] */
   double G;               /* interaction strength, < 0 [-1.0] */
   double A;               /* hybrid-force parameter of Eq. 9 [-0.6]; 0 = plain Shan-Chen force (Eq. 7) */
@@ -83,6 +93,9 @@ typedef struct {
   double rho0_shift;      /* LBM_F32_SHIFTED: reference density rho0 of the stored f_i - w_i rho0 */
   double rho_fp64_below;  /* FP32 modes: the EOS / psi is evaluated in FP64 where rho < this; 0 = never */
   double body_force[2];   /* constant body force per unit volume (F_g of Eq. 7) [0, 0] */
+  double pw_theta[3];     /* LBM_EOS_PIECEWISE_LINEAR: theta_v, theta_m, theta_l of Eq. 11 (Table 1: e.g.
+                             0.25, -0.02, 0.3 for a density ratio of 10) */
+  double pw_rho[2];       /* LBM_EOS_PIECEWISE_LINEAR: rho_v, rho_l (Eq. 12-13), e.g. 1 and 10 */
 } lbm_params;
 
 /* Device diagnostics of one instance, accumulated by the periodic checks (check_every) of lbm_step. */
@@ -109,9 +122,10 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
 
 int lbm_destroy(lbm_ctx* c);
 
-/* Host FP64 EOS data of instance inst: out[0] = rho_v, out[1] = rho_l (Maxwell equal-area coexistence of the
- * Carnahan-Starling EOS), out[2] = T (absolute), out[3] = T_c, out[4] = rho_c, out[5] = rho_cap (largest
- * density with real psi, Eq. 10). */
+/* Host FP64 EOS data of instance inst. Carnahan-Starling: out[0] = rho_v, out[1] = rho_l (Maxwell equal-area
+ * coexistence), out[2] = T (absolute), out[3] = T_c, out[4] = rho_c. Piecewise linear: out[0], out[1] = pw_rho,
+ * out[2] = rho_1, out[3] = rho_2 (the break points of Eq. 12-13), out[4] = 0. Both: out[5] = rho_cap, the largest
+ * density with real psi (Eq. 10), or 1e300 where psi is real at every density above the vapour. */
 int lbm_eos_info(const lbm_ctx* c, int32_t inst, double out[6]);
 
 /* Initial state (droplets at rest): rho(x, y) = rho_v + (rho_l - rho_v) (1 - tanh(2 (r - R_k)/width)) / 2,

@@ -14,10 +14,11 @@ class Params(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32), ("wet_iters", C.c_int32),
         ("check_every", C.c_int32), ("strip_rows", C.c_int32), ("enable_adjoint", C.c_int32),
-        ("step_variant", C.c_int32), ("boundary", C.c_int32), ("reserved", C.c_int32),
+        ("step_variant", C.c_int32), ("boundary", C.c_int32), ("eos", C.c_int32),
         ("tau", C.c_double), ("G", C.c_double), ("A", C.c_double),
         ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("T_over_Tc", C.c_double),
         ("rho0_shift", C.c_double), ("rho_fp64_below", C.c_double), ("body_force", C.c_double * 2),
+        ("pw_theta", C.c_double * 3), ("pw_rho", C.c_double * 2),
     ]
 
 

@@ -29,8 +29,10 @@ namespace {
 constexpr int AB = 256;          // block size
 constexpr int kAdjBlocks = 1024; // grid of the reductions (grid-stride)
 
-__device__ inline double dp_cs(const InstDesc& d, double rho) {
-  // dp/drho of Carnahan-Starling: R T (1 + 4e + 4e^2 - 4e^3 + e^4)/(1 - e)^4 - 2 a rho, e = b rho / 4
+__device__ inline double dp_drho(const InstDesc& d, double rho) {
+  // Eq. 11: the slope of the segment that the forward pass evaluated (same comparisons)
+  if (d.eos_kind == 1) return rho <= d.pw_r1 ? d.pw_t[0] : (rho <= d.pw_r2 ? d.pw_t[1] : d.pw_t[2]);
+  // Carnahan-Starling: R T (1 + 4e + 4e^2 - 4e^3 + e^4)/(1 - e)^4 - 2 a rho, e = b rho / 4
   const double e = d.eos_b4 * rho, om = 1.0 - e;
   const double om2 = om * om;
   return d.RT * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om2 * om2) - 2.0 * d.eos_a * rho;
@@ -39,7 +41,7 @@ __device__ inline double dp_cs(const InstDesc& d, double rho) {
 // d psi / d rho where psi > 0 (Eq. 10): (p'(rho) - 1/3) / (G_psi psi); 0 where psi was clamped.
 __device__ inline double dpsi_drho(const InstDesc& d, double rho, double psi) {
   if (!(psi > 0.0)) return 0.0;
-  return (dp_cs(d, rho) - 1.0 / 3.0) * (0.5 * d.two_over_Gpsi) / psi;
+  return (dp_drho(d, rho) - 1.0 / 3.0) * (0.5 * d.two_over_Gpsi) / psi;
 }
 
 struct Field {
@@ -66,9 +68,9 @@ __global__ __launch_bounds__(AB) void ka_prep(const InstDesc* __restrict__ descs
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int64_t n = (int64_t)nx * (ny - 2);
-  const int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x;
-  if (k >= n) return;
-  const int x = (int)(k % nx), y = (int)(k / nx) + 1;
+  const unsigned k = blockIdx.x * AB + threadIdx.x;  // node counts are below 2^31 (lbm_create checks)
+  if (k >= (unsigned)n) return;
+  const int x = (int)(k % (unsigned)nx), y = (int)(k / (unsigned)nx) + 1;
   double r = f[k];
 #pragma unroll
   for (int i = 1; i < 9; ++i) r += f[i * n + k];
@@ -120,8 +122,8 @@ __global__ __launch_bounds__(AB) void ka_collide(const InstDesc* __restrict__ de
   const int64_t n = (int64_t)nx * (ny - 2);
   Field P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
   double gf_part = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x; k < n; k += (int64_t)gridDim.x * AB) {
-    const int x = (int)(k % nx), y = (int)(k / nx) + 1;
+  for (unsigned k = blockIdx.x * AB + threadIdx.x; k < (unsigned)n; k += gridDim.x * AB) {
+    const int x = (int)(k % (unsigned)nx), y = (int)(k / (unsigned)nx) + 1;
     double fl[9], ls[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -264,8 +266,8 @@ __global__ __launch_bounds__(AB) void ka_psi(const InstDesc* __restrict__ descs,
   const int64_t n = (int64_t)nx * (ny - 2);
   Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
   double gpsi = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x; k < n; k += (int64_t)gridDim.x * AB) {
-    const int x = (int)(k % nx), y = (int)(k / nx) + 1;
+  for (unsigned k = blockIdx.x * AB + threadIdx.x; k < (unsigned)n; k += gridDim.x * AB) {
+    const int x = (int)(k % (unsigned)nx), y = (int)(k / (unsigned)nx) + 1;
     const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
     // own force: d F(x) / d psi(x) = -G_f (1 - A) sum_a w_a psi(x + e_a) e_a
     const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0;

@@ -152,6 +152,58 @@ double cs_rho_cap(const Eos& E, double rho_c) {
   return safe_root(h, [&](double r) { return E.dp(r) - 1.0 / 3.0; }, lo, top);
 }
 
+// Piecewise-linear EOS (Eq. 11) with slopes t = (theta_v, theta_m, theta_l) and break points r1 < r2.
+struct PwEos {
+  double tv, tm, tl, r1 = 0, r2 = 0;
+  double p(double rho) const {
+    if (rho <= r1) return rho * tv;
+    if (rho <= r2) return r1 * tv + (rho - r1) * tm;
+    return r1 * tv + (r2 - r1) * tm + (rho - r2) * tl;
+  }
+};
+
+// Break points for the coexistence pair (rv, rl). Eq. 12 is linear in (r1, r2): r1 = (tv rv + (tl - tm) r2 -
+// tl rl) / (tv - tm). Eq. 13 is then a function of r2 alone, bisected over the r2 for which rv < r1 < r2 < rl.
+bool pw_solve(PwEos* E, double rv, double rl) {
+  const double tv = E->tv, tm = E->tm, tl = E->tl;
+  auto r1_of = [&](double r2) { return (tv * rv + (tl - tm) * r2 - tl * rl) / (tv - tm); };
+  auto eq13 = [&](double r2) {
+    const double r1 = r1_of(r2);
+    return tv * std::log(r1 / rv) + tm * std::log(r2 / r1) + tl * std::log(rl / r2);
+  };
+  double lo = (tl * rl - tm * rv) / (tl - tm);             // r1 = rv here
+  if (tl < tv) lo = std::max(lo, (tv * rv - tl * rl) / (tv - tl));  // r1 = r2 here
+  double hi = rl;
+  if (tl > tv) hi = std::min(hi, (tl * rl - tv * rv) / (tl - tv));
+  if (!(lo < hi)) return false;
+  const double span = hi - lo;
+  lo += 1e-14 * span;
+  hi -= 1e-14 * span;
+  double hl = eq13(lo), hh = eq13(hi);
+  if (!std::isfinite(hl) || !std::isfinite(hh) || (hl > 0) == (hh > 0)) return false;
+  for (int it = 0; it < 400 && hi - lo > 1e-16 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double hm = eq13(mid);
+    if (hm == 0.0) { lo = hi = mid; break; }
+    if ((hm > 0) == (hl > 0)) { lo = mid; hl = hm; } else { hi = mid; }
+  }
+  E->r2 = 0.5 * (lo + hi);
+  E->r1 = r1_of(E->r2);
+  return rv < E->r1 && E->r1 < E->r2 && E->r2 < rl;
+}
+
+// Largest density with real psi (Eq. 10, G < 0: p <= rho/3). p - rho/3 falls on the vapour and unstable branches
+// (theta_v < 1/3, theta_m < 0), so only a liquid slope above 1/3 brings it back to 0.
+double pw_rho_cap(const PwEos& E) {
+  if (!(E.tl > 1.0 / 3.0)) return 1e300;
+  return E.r2 + (E.r2 / 3.0 - E.p(E.r2)) / (E.tl - 1.0 / 3.0);
+}
+
+bool pw_from_params(const lbm_params& q, PwEos* E) {
+  *E = PwEos{q.pw_theta[0], q.pw_theta[1], q.pw_theta[2]};
+  return pw_solve(E, q.pw_rho[0], q.pw_rho[1]);
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Measured defaults on MI355X (autotuning can refine them per context): FP32 8 wavefronts per block with
@@ -168,13 +220,14 @@ constexpr bool kDefaultPrefetch64 = false;
 constexpr int kMinDefaultStripRows = 2;
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
-static_assert(sizeof(lbm_params) == 10 * 4 + 11 * 8, "lbm_params layout: 10 int32 then 11 double, no padding");
+static_assert(sizeof(lbm_params) == 10 * 4 + 16 * 8, "lbm_params layout: 10 int32 then 16 double, no padding");
 
 struct Inst {
   lbm_params p;
   int pitch = 0;
   int64_t plane = 0;
   double rho_c = 0, T_c = 0, T = 0, rho_v = 0, rho_l = 0, rho_cap = 0;
+  double pw_r1 = 0, pw_r2 = 0;  // piecewise-linear EOS break points
   int strip_rows = kDefaultStripRows;
   bool initialized = false;
   int64_t steps = 0;
@@ -220,14 +273,29 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.strip_rows < 0) return bad("strip_rows < 0");
     if (q.step_variant < 0 || q.step_variant > 2 * kNumWaveChoices) return bad("step_variant outside [0, 8]");
     if (q.boundary != LBM_WALLS_Y && q.boundary != LBM_PERIODIC_Y) return bad("unknown boundary");
-    if (q.reserved != 0) return bad("reserved must be 0");
+    if (q.eos != LBM_EOS_CARNAHAN_STARLING && q.eos != LBM_EOS_PIECEWISE_LINEAR) return bad("unknown eos");
     if (q.boundary == LBM_PERIODIC_Y && q.enable_adjoint) return bad("the adjoint supports LBM_WALLS_Y only");
     if ((int64_t)((q.nx + 63) / 64 * 64) * (q.ny - 2) * 9 >= ((int64_t)1 << 31)) return bad("lattice too large for 32-bit offsets");
     if (!(q.tau > 0.5) || !std::isfinite(q.tau)) return bad("tau must be > 0.5");
     if (!(q.G < 0) || !std::isfinite(q.G)) return bad("G must be negative");
     if (!std::isfinite(q.A)) return bad("A not finite");
-    if (!(q.eos_a > 0) || !(q.eos_b > 0) || !(q.eos_R > 0)) return bad("EOS constants must be positive");
-    if (!(q.T_over_Tc > 0 && q.T_over_Tc < 1)) return bad("T_over_Tc must be in (0, 1)");
+    if (q.eos == LBM_EOS_CARNAHAN_STARLING) {
+      if (!(q.eos_a > 0) || !(q.eos_b > 0) || !(q.eos_R > 0)) return bad("EOS constants must be positive");
+      if (!(q.T_over_Tc > 0 && q.T_over_Tc < 1)) return bad("T_over_Tc must be in (0, 1)");
+    } else {
+      const double* t = q.pw_theta;
+      if (!(t[0] > 0 && t[0] < 1.0 / 3.0)) return bad("piecewise EOS: theta_v must be in (0, 1/3)");
+      if (!(t[1] < 0) || !std::isfinite(t[1])) return bad("piecewise EOS: theta_m must be negative");
+      if (!(t[2] > 0) || !std::isfinite(t[2])) return bad("piecewise EOS: theta_l must be positive");
+      if (!(q.pw_rho[0] > 0 && q.pw_rho[1] > q.pw_rho[0] && std::isfinite(q.pw_rho[1])))
+        return bad("piecewise EOS: need 0 < rho_v < rho_l");
+      PwEos E;
+      // With these signs Eq. 13 changes sign across the feasible break points (the integral of dp / rho is negative
+      // where p falls first and positive where it rises first), so a failure here means degenerate input (theta_m or
+      // rho_l / rho_v - 1 at round-off level). psi is then real up to rho_l: p(rho_l) = p(rho_v) = theta_v rho_v
+      // < rho_l / 3.
+      if (!pw_from_params(q, &E)) return bad("piecewise EOS: Eq. 12-13 have no break points rho_v < rho_1 < rho_2 < rho_l");
+    }
     if (!std::isfinite(q.rho0_shift) || q.rho0_shift < 0) return bad("rho0_shift must be >= 0");
     if (q.precision != LBM_F32_SHIFTED && q.rho0_shift != 0) return bad("rho0_shift needs LBM_F32_SHIFTED");
     if (!std::isfinite(q.rho_fp64_below)) return bad("rho_fp64_below not finite");
@@ -397,14 +465,24 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     I.plane = (int64_t)I.pitch * (p[i].ny - 2);
     I.strip_rows = p[i].strip_rows > 0 ? p[i].strip_rows
                                         : (p[i].precision == LBM_F64 ? kDefaultStripRows64 : kDefaultStripRows);
-    cs_critical(p[i].eos_a, p[i].eos_b, p[i].eos_R, &I.rho_c, &I.T_c);
-    I.T = p[i].T_over_Tc * I.T_c;
-    Eos E{p[i].eos_a, p[i].eos_b, p[i].eos_R, I.T};
-    if (!cs_maxwell(E, I.rho_c, &I.rho_v, &I.rho_l)) {
-      delete c;
-      return fail(LBM_E_INVALID, "instance %d: no coexistence found", i);
+    PwEos pw{};
+    if (p[i].eos == LBM_EOS_PIECEWISE_LINEAR) {
+      pw_from_params(p[i], &pw);  // solvable: checked by valid_params
+      I.rho_v = p[i].pw_rho[0];
+      I.rho_l = p[i].pw_rho[1];
+      I.rho_cap = pw_rho_cap(pw);
+    } else {
+      cs_critical(p[i].eos_a, p[i].eos_b, p[i].eos_R, &I.rho_c, &I.T_c);
+      I.T = p[i].T_over_Tc * I.T_c;
+      Eos E{p[i].eos_a, p[i].eos_b, p[i].eos_R, I.T};
+      if (!cs_maxwell(E, I.rho_c, &I.rho_v, &I.rho_l)) {
+        delete c;
+        return fail(LBM_E_INVALID, "instance %d: no coexistence found", i);
+      }
+      I.rho_cap = cs_rho_cap(E, I.rho_c);
     }
-    I.rho_cap = cs_rho_cap(E, I.rho_c);
+    I.pw_r1 = pw.r1;
+    I.pw_r2 = pw.r2;
     for (int k = 0; k < 2; ++k) I.off_f[k] = L.inst_f[k][i];
     I.off_th = L.inst_th[i];
     I.off_ghost = L.inst_ghost[i];
@@ -443,6 +521,14 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     d.rho0 = p[i].precision == LBM_F32_SHIFTED ? p[i].rho0_shift : 0.0;
     d.rho_fp64_below = p[i].precision == LBM_F64 ? 0.0 : p[i].rho_fp64_below;
     d.rho_cap_hi = I.rho_cap * (1.0 - 1e-6);
+    d.eos_kind = p[i].eos;
+    if (p[i].eos == LBM_EOS_PIECEWISE_LINEAR) {
+      for (int k = 0; k < 3; ++k) d.pw_t[k] = p[i].pw_theta[k];
+      d.pw_r1 = pw.r1;
+      d.pw_r2 = pw.r2;
+      d.pw_p1 = pw.p(pw.r1);
+      d.pw_p2 = pw.p(pw.r2);
+    }
   }
   {
     // default strip height from the total work (see kDefaultStripRows)
@@ -505,9 +591,10 @@ int lbm_eos_info(const lbm_ctx* c, int32_t inst, double out[6]) {
   const Inst& I = c->inst[inst];
   out[0] = I.rho_v;
   out[1] = I.rho_l;
-  out[2] = I.T;
-  out[3] = I.T_c;
-  out[4] = I.rho_c;
+  const bool pw = I.p.eos == LBM_EOS_PIECEWISE_LINEAR;
+  out[2] = pw ? I.pw_r1 : I.T;
+  out[3] = pw ? I.pw_r2 : I.T_c;
+  out[4] = pw ? 0.0 : I.rho_c;
   out[5] = I.rho_cap;
   return LBM_OK;
 }

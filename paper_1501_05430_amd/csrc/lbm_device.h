@@ -37,14 +37,28 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
 // ------------------------------------------------------------------------------------------------ EOS / psi
-// Carnahan-Starling p(rho) and psi = sqrt(2 (p - rho/3) / G) (Eq. 10 with c = 1); the argument is clamped at 0
-// (counted) where it is negative.
+// p(rho) of the instance's EOS and psi = sqrt(2 (p - rho/3) / G) (Eq. 10 with c = 1); the argument is clamped at
+// 0 (counted) where it is negative. The EOS is Carnahan-Starling or the piecewise-linear one of Eq. 11; the choice
+// is per instance, so uniform over a block.
+
+// Eq. 11: the segment is chosen by rho <= rho_1, rho <= rho_2, else the liquid branch.
+template <class T>
+__device__ inline T pw_pressure(const InstDesc& d, T rho) {
+  if (rho <= (T)d.pw_r1) return rho * (T)d.pw_t[0];
+  if (rho <= (T)d.pw_r2) return (T)d.pw_p1 + (rho - (T)d.pw_r1) * (T)d.pw_t[1];
+  return (T)d.pw_p2 + (rho - (T)d.pw_r2) * (T)d.pw_t[2];
+}
 
 // FP64 mode: IEEE division and square root.
 __device__ inline double psi_f64(const InstDesc& d, double rho, bool& clamped) {
-  const double eta = d.eos_b4 * rho;
-  const double om = 1.0 - eta;
-  const double p = rho * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) / (om * om * om) - d.eos_a * rho * rho;
+  double p;
+  if (d.eos_kind == 1) {
+    p = pw_pressure(d, rho);
+  } else {
+    const double eta = d.eos_b4 * rho;
+    const double om = 1.0 - eta;
+    p = rho * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) / (om * om * om) - d.eos_a * rho * rho;
+  }
   double arg = d.two_over_Gpsi * (p - rho * (1.0 / 3.0));
   clamped = arg < 0.0;
   if (clamped) arg = 0.0;
@@ -72,19 +86,30 @@ __device__ inline double sqrt64(double x) {
 // FP32 modes: below rho_fp64_below the EOS is evaluated in FP64 (vapour side of a large density ratio),
 // elsewhere in FP32 with the hardware reciprocal and square root.
 __device__ inline float psi_f32(const InstDesc& d, float rho, bool& clamped) {
+  const bool pw = d.eos_kind == 1;
   if (rho < (float)d.rho_fp64_below) {
     const double r = (double)rho;
-    const double eta = d.eos_b4 * r;
-    const double om = 1.0 - eta;
-    const double p = r * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) * rcp64(om * om * om) - d.eos_a * r * r;
+    double p;
+    if (pw) {
+      p = pw_pressure(d, r);
+    } else {
+      const double eta = d.eos_b4 * r;
+      const double om = 1.0 - eta;
+      p = r * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) * rcp64(om * om * om) - d.eos_a * r * r;
+    }
     const double arg = d.two_over_Gpsi * (p - r * (1.0 / 3.0));
     clamped = arg < 0.0;
     return (float)sqrt64(arg);
   }
-  const float eta = (float)d.eos_b4 * rho;
-  const float om = 1.0f - eta;
-  const float p = rho * (float)d.RT * (1.0f + eta + eta * eta - eta * eta * eta) * __builtin_amdgcn_rcpf(om * om * om) -
-                  (float)d.eos_a * rho * rho;
+  float p;
+  if (pw) {
+    p = pw_pressure(d, rho);
+  } else {
+    const float eta = (float)d.eos_b4 * rho;
+    const float om = 1.0f - eta;
+    p = rho * (float)d.RT * (1.0f + eta + eta * eta - eta * eta * eta) * __builtin_amdgcn_rcpf(om * om * om) -
+        (float)d.eos_a * rho * rho;
+  }
   float arg = (float)d.two_over_Gpsi * (p - rho * (1.0f / 3.0f));
   clamped = arg < 0.0f;
   if (clamped) arg = 0.0f;

@@ -25,6 +25,10 @@ struct InstDesc {
   double rho0;              // storage shift (0 unless shifted FP32)
   double rho_fp64_below;    // FP32 modes: FP64 EOS below this density
   double rho_cap_hi;        // ghost density upper clamp, rho_cap (1 - 1e-6)
+  int32_t eos_kind, pad1;   // lbm_eos: 0 Carnahan-Starling (RT, eos_a, eos_b4), 1 piecewise linear (pw_*)
+  double pw_t[3];           // Eq. 11 slopes theta_v, theta_m, theta_l
+  double pw_r1, pw_r2;      // break points rho_1 < rho_2 (Eq. 12-13)
+  double pw_p1, pw_p2;      // p(rho_1) = rho_1 theta_v and p(rho_2) = p(rho_1) + (rho_2 - rho_1) theta_m
 };
 
 // One block's share of a step: columns [x0, x0+width) of rows [y0, y0+nrows) of instance inst

@@ -14,10 +14,17 @@ BOUNDARIES = {"walls": 0, "periodic": 1}
 
 def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=0, strip_rows=0,
                 enable_adjoint=False, step_variant=0, tau=1.0, G=-1.0, A=-0.6, eos_a=1.0, eos_b=4.0, eos_R=1.0, rho0_shift=0.0,
-                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls"):
+                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls", piecewise=None):
     """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'; boundary: 'walls'
-    (ghost rows 0 and ny-1 with the geometric wetting) or 'periodic' (fluid rows 1..ny-2 wrap around)."""
+    (ghost rows 0 and ny-1 with the geometric wetting) or 'periodic' (fluid rows 1..ny-2 wrap around).
+    piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the piecewise-linear EOS of Eq. 11 (break points
+    from Eq. 12-13; T_over_Tc and eos_a/b/R are then unused); None selects Carnahan-Starling."""
     p = Params()
+    if piecewise is not None:
+        p.eos = 1
+        for k in range(3):
+            p.pw_theta[k] = float(piecewise[k])
+        p.pw_rho[0], p.pw_rho[1] = float(piecewise[3]), float(piecewise[4])
     p.boundary = BOUNDARIES[boundary] if isinstance(boundary, str) else int(boundary)
     p.nx, p.ny = int(nx), int(ny)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -36,7 +43,8 @@ def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=
 
 
 def eos_coexistence(T_over_Tc, device="cuda:0", **eos):
-    """(rho_v, rho_l) of the library's Maxwell construction at T_over_Tc (a 16 x 8 probe context)."""
+    """(rho_v, rho_l) of the library's EOS (a 16 x 8 probe context): the Maxwell construction at T_over_Tc, or the
+    pair given with piecewise=."""
     with LBM(make_params(16, 8, T_over_Tc, **eos), device=device) as probe:
         info = probe.eos_info()
     return info["rho_v"], info["rho_l"]
@@ -120,6 +128,8 @@ class LBM:
         out = (C.c_double * 6)()
         check(self.lib.lbm_eos_info(self.ctx, inst, out))
         keys = ["rho_v", "rho_l", "T", "T_c", "rho_c", "rho_cap"]
+        if self.params[inst].eos == 1:
+            keys = ["rho_v", "rho_l", "rho_1", "rho_2", "_", "rho_cap"]
         return dict(zip(keys, list(out)))
 
     def init_droplet(self, xc, yc, R, inst=0, width=5.0, rho_l=0.0, rho_v=0.0):

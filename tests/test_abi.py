@@ -35,9 +35,10 @@ def test_binding_declares_every_entry_point():
 
 
 def test_params_struct_matches_header_size():
-    # lbm_params: 10 int32 + 11 double = 128 bytes, no padding
+    # lbm_params: 10 int32 + 16 double = 168 bytes, no padding
     from paper_1501_05430_amd import _lib
-    assert C.sizeof(_lib.Params) == 10 * 4 + 11 * 8
+    assert C.sizeof(_lib.Params) == 10 * 4 + 16 * 8
+    assert _lib.Params.pw_theta.offset == 10 * 4 + 11 * 8
 
 
 def test_workspace_bytes_and_validation():
@@ -66,6 +67,36 @@ def test_workspace_bytes_and_validation():
     # mixed precisions in one context are rejected
     with pytest.raises(P.LbmError):
         P.workspace_bytes([p, p32])
+    q = P.make_params(20, 10, 0.8)
+    q.eos = 2
+    with pytest.raises(P.LbmError):
+        P.workspace_bytes(q)
+
+
+TABLE1 = [(0.25, -0.02, 0.3, 1.0, 10.0), (0.1633, -0.02, 0.33333, 1.0, 100.0), (0.2, -0.01, 0.33333, 1.0, 1000.0)]
+
+
+@pytest.mark.parametrize("pw", TABLE1)
+def test_piecewise_eos_params_accepted(pw):
+    import paper_1501_05430_amd as P
+    # T_over_Tc is unused with the piecewise EOS (here outside (0, 1) on purpose)
+    for precision in ("f64", "f32_shifted"):
+        assert P.workspace_bytes(P.make_params(64, 32, 2.0, precision=precision, piecewise=pw)) > 0
+
+
+@pytest.mark.parametrize("pw,why", [
+    ((1 / 3, -0.02, 0.3, 1.0, 10.0), "theta_v"),         # psi imaginary on the vapour branch
+    ((0.25, 0.0, 0.3, 1.0, 10.0), "theta_m"),            # no unstable branch
+    ((0.25, -0.02, 0.0, 1.0, 10.0), "theta_l"),
+    ((0.25, -0.02, 0.3, 10.0, 1.0), "rho_v < rho_l"),
+    ((0.25, -0.02, 0.3, 0.0, 10.0), "rho_v < rho_l"),
+    ((0.25, -1e-9, 1000.0, 1.0, 1.0001), "break points"),  # degenerate: no root resolvable in double precision
+])
+def test_piecewise_eos_params_rejected(pw, why):
+    import paper_1501_05430_amd as P
+    with pytest.raises(P.LbmError) as e:
+        P.workspace_bytes(P.make_params(64, 32, 0.8, piecewise=pw))
+    assert why in str(e.value)
 
 
 def test_product_path_refuses_without_gpu():
@@ -75,3 +106,27 @@ def test_product_path_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         P.LBM(P.make_params(20, 10, 0.8))
+
+
+def test_piecewise_eos_acceptance_matches_reference(ora):
+    """Over a grid of slopes and density ratios (all solvable, including liquid slopes above 1/3 where psi has a
+    cap) the library accepts exactly the parameter sets for which the reference solves Eq. 12-13 with psi real up
+    to rho_l (the two solvers eliminate different unknowns)."""
+    import itertools
+    import paper_1501_05430_amd as P
+    n_ok = 0
+    for tv, tm, tl, rl in itertools.product([0.05, 0.25, 0.33], [-0.001, -0.02, -0.5, -5.0], [0.01, 0.3, 1.0, 10.0],
+                                            [1.01, 2.0, 10.0, 1000.0]):
+        try:
+            r1, r2 = ora.pw_breakpoints(tv, tm, tl, 1.0, rl)
+            ref_ok = ora.pw_rho_cap(tv, tm, tl, r1, r2) > rl
+        except ValueError:
+            ref_ok = False
+        try:
+            P.workspace_bytes(P.make_params(16, 8, 0.5, piecewise=(tv, tm, tl, 1.0, rl)))
+            lib_ok = True
+        except P.LbmError:
+            lib_ok = False
+        assert lib_ok == ref_ok, (tv, tm, tl, rl)
+        n_ok += lib_ok
+    assert n_ok == 192
