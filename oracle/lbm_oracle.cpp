@@ -13,7 +13,14 @@
 //  * Lattice: D2Q9 in the moment order of Eq. (4): e0=(0,0), e1..e4=(1,0),(0,1),(-1,0),(0,-1),
 //    e5..e8=(1,1),(-1,1),(-1,-1),(1,-1); lattice weights 4/9, 1/9, 1/36, c_s^2 = 1/3.
 //  * Collision: Eq. (1)-(6) with the relaxation matrix of Sec. 3.1, diag(0,1,...,1), equal BGK with tau = 1 and
-//    Guo forcing; tau is kept general (BGK), with v = (j + F/2)/rho.
+//    Guo forcing; tau is kept general (BGK), with v = (j + F/2)/rho. The last entry of Eq. (6) is the forcing's
+//    second moment, v_x F_y + v_y F_x.
+//  * MRT (mrt = 1): Eq. (15) in moment space with Lambda of Eq. (2) = diag(0, s_e, s_eps, 1, s_q, 1, s_q, 1/tau,
+//    1/tau) and the surface-tension source C of Eq. (16) with Q_3 = 0; the eighth entry of C is
+//    -(1/tau)(Q_xx - Q_yy), the factor of the ninth (the two entries are the deviatoric parts of one tensor). Q of
+//    Eq. (17) carries the factor G/2: with it the source scales the anisotropic part of the pressure tensor by
+//    1 - kappa and keeps its normal part, so the surface tension goes as 1 - kappa as the paper states (as printed,
+//    without G/2, it would go as 1 + 2 kappa at G = -1).
 //  * Force: Eq. (9) (Kupershtokh hybrid, parameter A) with the weights of Eq. (7), w(1)=1/3, w(2)=1/12, and
 //    U = G psi^2 / 2 (Eq. 8). A = 0 is the plain Shan-Chen force of Eq. (7).
 //  * psi from Eq. (10) with c = 1: psi = sqrt(2 (p_EOS(rho) - rho/3) / G); p_EOS is Carnahan-Starling, or the
@@ -79,6 +86,10 @@ typedef struct {
   int32_t pad;
   double pw_theta_v, pw_theta_m, pw_theta_l;  // Eq. (11): slopes of the vapour, unstable and liquid branches
   double pw_rho1, pw_rho2;                    // Eq. (11): break points (from Eq. 12-13, ora_pw_breakpoints)
+  int32_t mrt;           // 0: BGK (above); 1: MRT collision of Eq. (15) with the rates below and 1/tau for the stress
+  int32_t pad2;
+  double s_e, s_eps, s_q;  // Eq. (2): tau_e^-1, tau_xi^-1, tau_q^-1 (MRT only)
+  double kappa;            // Eq. (17): surface-tension parameter (MRT only; 0 = no source C)
 } ora_params;
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -285,6 +296,46 @@ double ora_pw_rho_cap(double tv, double tm, double tl, double r1, double r2) {
 // ---------------------------------------------------------------------------------------------------------------
 namespace {
 
+// Orthogonal D2Q9 moment matrix in the moment order of Eq. (4): rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy.
+const int MM[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1},
+};
+
+// Q of Eq. (17) at node (x, y) from a psi field [ny][nx] (neighbours wrap in x, and in y when periodic), with the
+// factor G/2 (see the file header): Q = kappa (G/2) [(1 - A) psi(x) sum_a w_a (psi(x+e_a) - psi(x)) e_a e_a
+//                                                 + (A/2) sum_a w_a (psi(x+e_a)^2 - psi(x)^2) e_a e_a].
+template <class S>
+void qtensor_at(const ora_params& p, const S& G, const S* psi, int nx, int ny, int x, int y, S* qxx, S* qyy,
+                S* qxy) {
+  S pc = psi[(size_t)y * nx + x];
+  S a_xx = 0.0, a_yy = 0.0, a_xy = 0.0, b_xx = 0.0, b_yy = 0.0, b_xy = 0.0;
+  for (int a = 1; a < 9; ++a) {
+    int xn = wrap(x + EX[a], nx);
+    int yn = p.periodic_y ? wrap(y + EY[a], ny) : y + EY[a];
+    S pn = psi[(size_t)yn * nx + xn];
+    S d1 = WF[a] * (pn - pc);
+    S d2 = WF[a] * (pn * pn - pc * pc);
+    a_xx += d1 * (double)(EX[a] * EX[a]);
+    a_yy += d1 * (double)(EY[a] * EY[a]);
+    a_xy += d1 * (double)(EX[a] * EY[a]);
+    b_xx += d2 * (double)(EX[a] * EX[a]);
+    b_yy += d2 * (double)(EY[a] * EY[a]);
+    b_xy += d2 * (double)(EX[a] * EY[a]);
+  }
+  S k = p.kappa * G / 2.0;
+  *qxx = k * ((1.0 - p.A) * pc * a_xx + p.A / 2.0 * b_xx);
+  *qyy = k * ((1.0 - p.A) * pc * a_yy + p.A / 2.0 * b_yy);
+  *qxy = k * ((1.0 - p.A) * pc * a_xy + p.A / 2.0 * b_xy);
+}
+
 struct Counters {
   int64_t ghost_clamps = 0;
   int64_t psi_clamps = 0;
@@ -428,7 +479,13 @@ struct Oracle {
         Fx += p.body_fx;
         Fy += p.body_fy;
         S fstar[9];
-        collide_node(f + k * 9, rho[k], jx[k], jy[k], Fx, Fy, fstar);
+        if (p.mrt) {
+          S qxx, qyy, qxy;
+          qtensor_at(p, G_f, psi.data(), nx, ny, x, y, &qxx, &qyy, &qxy);
+          collide_mrt(f + k * 9, rho[k], jx[k], jy[k], Fx, Fy, qxx, qyy, qxy, fstar);
+        } else {
+          collide_node(f + k * 9, rho[k], jx[k], jy[k], Fx, Fy, fstar);
+        }
         for (int i = 0; i < 9; ++i) {
           int xd = wrap(x + EX[i], nx);
           int yd = y + EY[i];
@@ -458,6 +515,39 @@ struct Oracle {
       fstar[i] = fn[i] - (fn[i] - feq) / p.tau + Fi;
     }
   }
+
+  // MRT collision of Eq. (15): m = M f; m* = m - Lambda (m - m_eq) + (I - Lambda/2) S + C; f* = M^-1 m*, with
+  // m_eq of Eq. (4) at v = (j + F/2)/rho, S of Eq. (6), C of Eq. (16) and M^-1 = M^T diag(1 / |row|^2).
+  void collide_mrt(const S* fn, const S& r, const S& mx, const S& my, const S& Fx, const S& Fy, const S& qxx,
+                   const S& qyy, const S& qxy, S* fstar) const {
+    S m[9];
+    for (int k = 0; k < 9; ++k) {
+      m[k] = 0.0;
+      for (int i = 0; i < 9; ++i) m[k] += (double)MM[k][i] * fn[i];
+    }
+    S vx = (mx + Fx / 2.0) / r;
+    S vy = (my + Fy / 2.0) / r;
+    S vv = vx * vx + vy * vy;
+    S meq[9] = {r, r * (-2.0 + 3.0 * vv), r * (1.0 - 3.0 * vv), r * vx, -r * vx, r * vy, -r * vy,
+                r * (vx * vx - vy * vy), r * vx * vy};
+    S vf = vx * Fx + vy * Fy;
+    S src[9] = {S(0.0), 6.0 * vf, -6.0 * vf, Fx, -Fx, Fy, -Fy, 2.0 * (vx * Fx - vy * Fy), vx * Fy + vy * Fx};
+    const double s_nu = 1.0 / p.tau;
+    const double lam[9] = {0.0, p.s_e, p.s_eps, 1.0, p.s_q, 1.0, p.s_q, s_nu, s_nu};
+    S C[9] = {S(0.0), 1.5 * p.s_e * (qxx + qyy), S(0.0), S(0.0), S(0.0), S(0.0), S(0.0), -s_nu * (qxx - qyy),
+              -s_nu * qxy};
+    S ms[9];
+    for (int k = 0; k < 9; ++k) ms[k] = m[k] - lam[k] * (m[k] - meq[k]) + (1.0 - lam[k] / 2.0) * src[k] + C[k];
+    for (int i = 0; i < 9; ++i) {
+      S v = 0.0;
+      for (int k = 0; k < 9; ++k) {
+        int nk = 0;
+        for (int j = 0; j < 9; ++j) nk += MM[k][j] * MM[k][j];
+        v += (double)MM[k][i] * ms[k] / (double)nk;
+      }
+      fstar[i] = v;
+    }
+  }
 };
 
 template <class S>
@@ -479,6 +569,8 @@ void run_steps(const ora_params& p, S G_f, S G_psi, S* f, int64_t nsteps, const 
 bool params_ok(const ora_params* p) {
   if (!p || p->nx < 1 || p->ny < (p->periodic_y ? 1 : 4) || p->wet_iters < 0) return false;
   if (!(p->tau > 0.5) || !(p->G < 0)) return false;
+  if (p->mrt && !(p->s_e > 0 && p->s_e < 2 && p->s_eps > 0 && p->s_eps < 2 && p->s_q > 0 && p->s_q < 2)) return false;
+  if (!p->mrt && p->kappa != 0.0) return false;
   if (p->eos_kind == 1)
     return p->pw_theta_v > 0 && p->pw_theta_m < 0 && p->pw_theta_l > 0 && p->pw_rho1 > 0 && p->pw_rho2 > p->pw_rho1;
   return p->eos_kind == 0 && p->T > 0;
@@ -550,6 +642,37 @@ int ora_collide_node(const ora_params* p, const double* f_in, double Fx, double 
     my += f_in[i] * EY[i];
   }
   o.collide_node(f_in, r, mx, my, Fx, Fy, f_out);
+  return 0;
+}
+
+// One MRT collision of a single node (Eq. 15) given the total force and the tensor Q of Eq. (17).
+int ora_collide_mrt_node(const ora_params* p, const double* f_in, double Fx, double Fy, const double* Q,
+                         double* f_out) {
+  if (!params_ok(p) || !p->mrt) return 1;
+  Oracle<double> o(*p, p->G, p->G);
+  double r = 0, mx = 0, my = 0;
+  for (int i = 0; i < 9; ++i) {
+    r += f_in[i];
+    mx += f_in[i] * EX[i];
+    my += f_in[i] * EY[i];
+  }
+  o.collide_mrt(f_in, r, mx, my, Fx, Fy, Q[0], Q[1], Q[2], f_out);
+  return 0;
+}
+
+// Q of Eq. (17) (with G/2, see the header) at every node of a psi field [ny][nx]: q[3][ny][nx] = Q_xx, Q_yy, Q_xy.
+// Rows 0 and ny-1 are skipped unless periodic_y (they are ghost rows).
+int ora_qtensor(const ora_params* p, const double* psi, double* q) {
+  if (!params_ok(p)) return 1;
+  const int nx = p->nx, ny = p->ny;
+  const size_t n = (size_t)nx * ny;
+  for (int y = 0; y < ny; ++y) {
+    if (!p->periodic_y && (y == 0 || y == ny - 1)) continue;
+    for (int x = 0; x < nx; ++x) {
+      const size_t k = (size_t)y * nx + x;
+      qtensor_at<double>(*p, p->G, psi, nx, ny, x, y, &q[k], &q[n + k], &q[2 * n + k]);
+    }
+  }
   return 0;
 }
 

@@ -22,6 +22,8 @@ class OraParams(C.Structure):
         ("eos_kind", C.c_int32), ("pad", C.c_int32),
         ("pw_theta_v", C.c_double), ("pw_theta_m", C.c_double), ("pw_theta_l", C.c_double),
         ("pw_rho1", C.c_double), ("pw_rho2", C.c_double),
+        ("mrt", C.c_int32), ("pad2", C.c_int32),
+        ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("kappa", C.c_double),
     ]
 
 
@@ -54,6 +56,8 @@ def lib():
         L.ora_pw_pressure.argtypes = [d, d, d, d, d, d]; L.ora_pw_pressure.restype = d
         L.ora_pw_breakpoints.argtypes = [d, d, d, d, d, p, p]; L.ora_pw_breakpoints.restype = C.c_int
         L.ora_pw_rho_cap.argtypes = [d, d, d, d, d]; L.ora_pw_rho_cap.restype = d
+        L.ora_collide_mrt_node.argtypes = [pp, p, d, d, p, p]; L.ora_collide_mrt_node.restype = C.c_int
+        L.ora_qtensor.argtypes = [pp, p, p]; L.ora_qtensor.restype = C.c_int
         _lib = L
     return _lib
 
@@ -128,9 +132,12 @@ class Sim:
     """One lattice (state in self.f, [ny, nx, 9] float64) advanced by the reference step."""
 
     def __init__(self, nx, ny, T_over_Tc, theta_bottom=np.pi / 2, theta_top=np.pi / 2, *, wet_iters=4, tau=1.0,
-                 G=-1.0, A=-0.6, a=1.0, b=4.0, R=1.0, body_force=(0.0, 0.0), periodic_y=False, piecewise=None):
+                 G=-1.0, A=-0.6, a=1.0, b=4.0, R=1.0, body_force=(0.0, 0.0), periodic_y=False, piecewise=None,
+                 mrt=None, kappa=0.0):
         """piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the EOS of Eq. (11) with the break points
-        of Eq. (12)-(13) (T_over_Tc is then unused); None selects Carnahan-Starling."""
+        of Eq. (12)-(13) (T_over_Tc is then unused); None selects Carnahan-Starling. mrt = (s_e, s_eps, s_q) selects
+        the MRT collision of Eq. (15) (the stress relaxes at 1/tau); kappa != 0 adds the source of Eq. (16)-(17) and
+        implies MRT (rates 1/tau where mrt is None)."""
         if piecewise is None:
             rc, tc, pc = cs_critical(a, b, R)
             self.T_c = tc
@@ -140,6 +147,11 @@ class Sim:
         self.p = OraParams(nx, ny, 1 if periodic_y else 0, wet_iters, tau, G, A, a, b, R, self.T,
                            body_force[0], body_force[1])
         self.piecewise = piecewise
+        if mrt is not None or kappa != 0.0:
+            rates = mrt if mrt is not None else (1.0 / tau,) * 3
+            self.p.mrt = 1
+            self.p.s_e, self.p.s_eps, self.p.s_q = (float(r) for r in rates)
+            self.p.kappa = float(kappa)
         if piecewise is not None:
             tv, tm, tl, rv, rl = piecewise
             r1, r2 = pw_breakpoints(tv, tm, tl, rv, rl)
@@ -214,6 +226,25 @@ class Sim:
         return fc
 
 
+def collide_mrt_node(sim, f_in, Fx, Fy, Q=(0.0, 0.0, 0.0)):
+    """One MRT collision (Eq. 15) of one node with total force (Fx, Fy) and Q = (Q_xx, Q_yy, Q_xy)."""
+    f_in = np.ascontiguousarray(f_in, dtype=np.float64)
+    q = np.ascontiguousarray(Q, dtype=np.float64)
+    out = np.zeros(9)
+    if lib().ora_collide_mrt_node(C.byref(sim.p), _ptr(f_in), float(Fx), float(Fy), _ptr(q), _ptr(out)):
+        raise ValueError("bad parameters (MRT off?)")
+    return out
+
+
+def qtensor(sim, psi):
+    """Q of Eq. (17) at every node of a psi field [ny, nx]: array [3, ny, nx] of Q_xx, Q_yy, Q_xy."""
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    q = np.zeros((3,) + psi.shape)
+    if lib().ora_qtensor(C.byref(sim.p), _ptr(psi), _ptr(q)):
+        raise ValueError("bad parameters")
+    return q
+
+
 def collide_node(sim, f_in, Fx, Fy):
     f_in = np.ascontiguousarray(f_in, np.float64)
     out = np.zeros(9)
@@ -231,5 +262,5 @@ def psi(sim, rho):
 
 
 __all__ = ["OraParams", "lib", "cs_pressure", "cs_dpdrho", "cs_d2pdrho2", "cs_mu", "cs_critical", "cs_maxwell",
-           "cs_rho_cap", "pw_breakpoints", "pw_pressure", "pw_rho_cap", "ghost_density", "Sim", "collide_node", "psi",
-           "num_threads"]
+           "cs_rho_cap", "pw_breakpoints", "pw_pressure", "pw_rho_cap", "ghost_density", "Sim", "collide_node",
+           "collide_mrt_node", "qtensor", "psi", "num_threads"]
