@@ -96,6 +96,12 @@ typedef struct {
   double pw_theta[3];     /* LBM_EOS_PIECEWISE_LINEAR: theta_v, theta_m, theta_l of Eq. 11 (Table 1: e.g.
                              0.25, -0.02, 0.3 for a density ratio of 10) */
   double pw_rho[2];       /* LBM_EOS_PIECEWISE_LINEAR: rho_v, rho_l (Eq. 12-13), e.g. 1 and 10 */
+  double mrt_rates[3];    /* s_e, s_eps, s_q of Eq. 2 (tau_e^-1, tau_xi^-1, tau_q^-1), each 0 (= 1/tau) or in
+                             (0, 2). Any non-zero rate, or kappa != 0, selects the MRT collision of Eq. 15 (stress
+                             relaxed at 1/tau; the conserved moments' rates do not enter); all 0 with kappa = 0 is
+                             BGK, the same scheme up to rounding. Excludes enable_adjoint. [0, 0, 0] */
+  double kappa;           /* surface-tension parameter of Eq. 16-17: the source C with Q = kappa (G/2)[...] scales
+                             the surface tension by 1 - kappa and leaves flat-interface densities unchanged. [0] */
 } lbm_params;
 
 /* Device diagnostics of one instance, accumulated by the periodic checks (check_every) of lbm_step. */

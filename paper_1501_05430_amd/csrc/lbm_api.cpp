@@ -206,6 +206,11 @@ bool pw_from_params(const lbm_params& q, PwEos* E) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// MRT collision (Eq. 15) when a rate of Eq. 2 or the surface-tension parameter kappa is set.
+bool uses_mrt(const lbm_params& q) {
+  return q.mrt_rates[0] != 0.0 || q.mrt_rates[1] != 0.0 || q.mrt_rates[2] != 0.0 || q.kappa != 0.0;
+}
+
 // Measured defaults on MI355X (autotuning can refine them per context): FP32 8 wavefronts per block with
 // prefetch, FP64 4 wavefronts without. Strip height: about two blocks per compute unit over all instances,
 // rows = round(fluid nodes / (2 CUs * 64 * waves)), within [2, 32] (FP32) / [2, 64] (FP64); this matches the
@@ -220,7 +225,7 @@ constexpr bool kDefaultPrefetch64 = false;
 constexpr int kMinDefaultStripRows = 2;
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
-static_assert(sizeof(lbm_params) == 10 * 4 + 16 * 8, "lbm_params layout: 10 int32 then 16 double, no padding");
+static_assert(sizeof(lbm_params) == 10 * 4 + 20 * 8, "lbm_params layout: 10 int32 then 20 double, no padding");
 
 struct Inst {
   lbm_params p;
@@ -300,6 +305,11 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.precision != LBM_F32_SHIFTED && q.rho0_shift != 0) return bad("rho0_shift needs LBM_F32_SHIFTED");
     if (!std::isfinite(q.rho_fp64_below)) return bad("rho_fp64_below not finite");
     if (!std::isfinite(q.body_force[0]) || !std::isfinite(q.body_force[1])) return bad("body force not finite");
+    for (int k = 0; k < 3; ++k)
+      if (!(q.mrt_rates[k] == 0.0 || (q.mrt_rates[k] > 0.0 && q.mrt_rates[k] < 2.0)))
+        return bad("mrt_rates must be 0 (= 1/tau) or in (0, 2)");
+    if (!std::isfinite(q.kappa)) return bad("kappa not finite");
+    if (uses_mrt(q) && q.enable_adjoint) return bad("the adjoint supports the BGK collision only (mrt_rates = 0, kappa = 0)");
   }
   return true;
 }
@@ -364,10 +374,10 @@ struct lbm_ctx {
   double* d_rho_scratch() { return (double*)(ws + L.rho_scratch); }
   int n() const { return (int)inst.size(); }
 
-  // the tau = 1 collision applies when every selected instance has tau == 1 exactly
+  // the tau = 1 BGK collision applies when every selected instance has tau == 1 exactly and no MRT rates
   bool tau1(int sel) const {
     for (int i = 0; i < n(); ++i)
-      if ((sel < 0 || i == sel) && inst[i].p.tau != 1.0) return false;
+      if ((sel < 0 || i == sel) && (inst[i].p.tau != 1.0 || uses_mrt(inst[i].p))) return false;
     return true;
   }
 
@@ -522,6 +532,11 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     d.rho_fp64_below = p[i].precision == LBM_F64 ? 0.0 : p[i].rho_fp64_below;
     d.rho_cap_hi = I.rho_cap * (1.0 - 1e-6);
     d.eos_kind = p[i].eos;
+    d.mrt = uses_mrt(p[i]) ? 1 : 0;
+    d.s_e = p[i].mrt_rates[0] != 0.0 ? p[i].mrt_rates[0] : 1.0 / p[i].tau;
+    d.s_eps = p[i].mrt_rates[1] != 0.0 ? p[i].mrt_rates[1] : 1.0 / p[i].tau;
+    d.s_q = p[i].mrt_rates[2] != 0.0 ? p[i].mrt_rates[2] : 1.0 / p[i].tau;
+    d.kq = 0.5 * p[i].kappa * p[i].G;
     if (p[i].eos == LBM_EOS_PIECEWISE_LINEAR) {
       for (int k = 0; k < 3; ++k) d.pw_t[k] = p[i].pw_theta[k];
       d.pw_r1 = pw.r1;

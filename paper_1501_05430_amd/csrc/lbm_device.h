@@ -182,6 +182,83 @@ __device__ inline void collide(const C (&f)[9], C rho, C delta, C Fx, C Fy, C in
   }
 }
 
+// MRT collision of Eq. 15 with Lambda = diag(0, s_e, s_eps, 1, s_q, 1, s_q, 1/tau, 1/tau) (Eq. 2), the forcing
+// (I - Lambda/2) S of Eq. 5-6 (last entry of S: v_x F_y + v_y F_x) and the surface-tension source C of Eq. 16
+// (Q_3 = 0; the eighth entry -(1/tau)(Q_xx - Q_yy), the ninth's factor). Moments in the order of Eq. 4 (rho, e,
+// eps, j_x, q_x, j_y, q_y, p_xx, p_xy). The change of every moment, dm_k = -s_k (m_k - m_eq,k) + (1 - s_k/2) S_k
+// + C_k, is mapped back with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) and added to f; the
+// momentum moments change by exactly F (v = (j + F/2)/rho). With storage shifted by w_i rho0 the equilibrium
+// moments of the stored populations are those of rho minus rho0 (1, -2, 1, 0, ...), i.e. delta = rho - rho0 in
+// the zeroth-order parts. Opposite pairs and the moments are formed so that the rounded result is exactly
+// mirror-symmetric (see sum9), and f*_0 comes from mass conservation as in collide().
+template <class C>
+__device__ inline void collide_mrt(const C (&f)[9], C rho, C delta, C Fx, C Fy, C irho, C s_e, C s_eps, C s_q,
+                                   C s_nu, C qxx, C qyy, C qxy, C (&fs)[9]) {
+#pragma clang fp contract(off)
+  const C dx = (f[5] - f[7]) + (f[8] - f[6]), dy = (f[5] - f[7]) + (f[6] - f[8]);  // diagonal parts of j
+  const C ax = f[1] - f[3], ay = f[2] - f[4];
+  const C jx = ax + dx, jy = ay + dy;
+  const C s13 = f[1] + f[3], s24 = f[2] + f[4];
+  const C sax = s13 + s24, sdg = (f[5] + f[7]) + (f[6] + f[8]);
+  const C m_e = (sdg + sdg) - (sax + (C)4 * f[0]);
+  const C m_eps = ((C)4 * f[0] + sdg) - (sax + sax);
+  const C m_qx = dx - (ax + ax), m_qy = dy - (ay + ay);
+  const C m_pxx = s13 - s24, m_pxy = (f[5] + f[7]) - (f[6] + f[8]);
+  const C vx = (jx + (C)0.5 * Fx) * irho, vy = (jy + (C)0.5 * Fy) * irho;
+  const C rv2 = (C)3 * rho * (vx * vx + vy * vy);
+  const C vF = vx * Fx + vy * Fy;
+  const C ce = (C)1.5 * s_e * (qxx + qyy);
+  const C de = -s_e * (m_e - (rv2 - (delta + delta))) + ((C)1 - (C)0.5 * s_e) * ((C)6 * vF) + ce;
+  const C deps = -s_eps * (m_eps - (delta - rv2)) - ((C)1 - (C)0.5 * s_eps) * ((C)6 * vF);
+  const C hq = (C)1 - (C)0.5 * s_q, hn = (C)1 - (C)0.5 * s_nu;
+  const C dqx = -s_q * (m_qx + rho * vx) - hq * Fx;
+  const C dqy = -s_q * (m_qy + rho * vy) - hq * Fy;
+  const C dpxx = -s_nu * (m_pxx - rho * (vx * vx - vy * vy)) + hn * ((C)2 * (vx * Fx - vy * Fy)) - s_nu * (qxx - qyy);
+  const C dpxy = -s_nu * (m_pxy - rho * (vx * vy)) + hn * (vx * Fy + vy * Fx) - s_nu * qxy;
+  const C a1 = de * (C)(1.0 / 36.0), a2 = deps * (C)(1.0 / 36.0);
+  const C a3 = Fx * (C)(1.0 / 6.0), a4 = dqx * (C)(1.0 / 12.0);
+  const C a5 = Fy * (C)(1.0 / 6.0), a6 = dqy * (C)(1.0 / 12.0);
+  const C a7 = dpxx * (C)0.25, a8 = dpxy * (C)0.25;
+  const C eax = -(a1 + (a2 + a2));            // even part on the axes
+  const C ox = a3 - (a4 + a4), oy = a5 - (a6 + a6);
+  fs[1] = f[1] + ((eax + a7) + ox);
+  fs[3] = f[3] + ((eax + a7) - ox);
+  fs[2] = f[2] + ((eax - a7) + oy);
+  fs[4] = f[4] + ((eax - a7) - oy);
+  const C ed = (a1 + a1) + a2;                // even part on the diagonals
+  const C X = a3 + a4, Y = a5 + a6;
+  fs[5] = f[5] + ((ed + a8) + (X + Y));
+  fs[7] = f[7] + ((ed + a8) - (X + Y));
+  fs[6] = f[6] + ((ed - a8) + (Y - X));
+  fs[8] = f[8] + ((ed - a8) - (Y - X));
+  const C d13 = (f[1] - fs[1]) + (f[3] - fs[3]), d24 = (f[2] - fs[2]) + (f[4] - fs[4]);
+  const C d57 = (f[5] - fs[5]) + (f[7] - fs[7]), d68 = (f[6] - fs[6]) + (f[8] - fs[8]);
+  fs[0] = f[0] + ((d13 + d24) + (d57 + d68));
+}
+
+// Q of Eq. 17 with the factor G/2 (kq = kappa G / 2): kq [(1 - A) psi sum_a w_a (psi_a - psi) e_a e_a
+// + (A/2) sum_a w_a (psi_a^2 - psi^2) e_a e_a] from the centre psi p, the row's neighbours pL, pR and the rows
+// above (n) and below (m). Grouped so that Q_xx, Q_yy are even and Q_xy odd, exactly, under both mirrors.
+template <class C>
+__device__ inline void qtensor(C p, C pL, C pR, C pn, C pnL, C pnR, C pm, C pmL, C pmR, C A, C kq, C& qxx, C& qyy,
+                               C& qxy) {
+#pragma clang fp contract(off)
+  const C k1 = (C)(1.0 / 3.0), k2 = (C)(1.0 / 12.0);
+  const C p2 = p * p;
+  const C dg1 = ((pnR + pnL) + (pmR + pmL)) - (C)4 * p;
+  const C dg2 = ((pnR * pnR + pnL * pnL) + (pmR * pmR + pmL * pmL)) - (C)4 * p2;
+  const C xx1 = k1 * ((pR + pL) - (p + p)) + k2 * dg1;
+  const C yy1 = k1 * ((pn + pm) - (p + p)) + k2 * dg1;
+  const C xy1 = k2 * ((pnR - pnL) - (pmR - pmL));
+  const C xx2 = k1 * ((pR * pR + pL * pL) - (p2 + p2)) + k2 * dg2;
+  const C yy2 = k1 * ((pn * pn + pm * pm) - (p2 + p2)) + k2 * dg2;
+  const C xy2 = k2 * ((pnR * pnR - pnL * pnL) - (pmR * pmR - pmL * pmL));
+  const C c1 = ((C)1 - A) * p, c2 = (C)0.5 * A;
+  qxx = kq * (c1 * xx1 + c2 * xx2);
+  qyy = kq * (c1 * yy1 + c2 * yy2);
+  qxy = kq * (c1 * xy1 + c2 * xy2);
+}
+
 // Ghost density of Sec. 4 in FP64: Eq. 19 (iters == 0) or the iters-th iterate of Eq. 21 with the square root of
 // Eq. 20. T is the tangential difference of the boundary row, D = rho_2 - rho_1. Clamped to [0, rho_cap_hi].
 __device__ inline double ghost_density(double rL, double rR, double r1, double r2, double c, double cot, int iters,

@@ -29,6 +29,9 @@ struct InstDesc {
   double pw_t[3];           // Eq. 11 slopes theta_v, theta_m, theta_l
   double pw_r1, pw_r2;      // break points rho_1 < rho_2 (Eq. 12-13)
   double pw_p1, pw_p2;      // p(rho_1) = rho_1 theta_v and p(rho_2) = p(rho_1) + (rho_2 - rho_1) theta_m
+  int32_t mrt, pad2;        // 1: MRT collision (Eq. 15) with the rates below, else BGK
+  double s_e, s_eps, s_q;   // Eq. 2 relaxation rates (the stress relaxes at inv_tau)
+  double kq;                // kappa G / 2 of Eq. 17 (0: no surface-tension source)
 };
 
 // One block's share of a step: columns [x0, x0+width) of rows [y0, y0+nrows) of instance inst

@@ -140,6 +140,9 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   const C A = (C)d.A, Gf = (C)d.G_f, inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
   const C bfx = (C)d.body_fx, bfy = (C)d.body_fy;
   const C k1 = (C)(1.0 / 3.0), k2 = (C)(1.0 / 12.0);
+  // MRT collision with the surface-tension source (never in the tau = 1 BGK specialisation)
+  const bool mrt = !TAU1 && d.mrt != 0, kap = mrt && d.kq != 0.0;
+  const C s_e = (C)d.s_e, s_eps = (C)d.s_eps, s_q = (C)d.s_q, kq = (C)d.kq;
 
   // The strip's rows are walked upwards (DOWN = false) or downwards. Consecutive launches alternate, so each
   // launch first reads the rows that the previous one wrote last, while they are still in the memory-side cache.
@@ -221,7 +224,13 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
         Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
       }
       C fs[9];
-      collide<C, TAU1>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
+      if (mrt) {
+        C qxx = (C)0, qyy = (C)0, qxy = (C)0;
+        if (kap) qtensor<C>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, A, kq, qxx, qyy, qxy);
+        collide_mrt<C>(fc, rc, rc - rho0, Fx, Fy, (C)1 / rc, s_e, s_eps, s_q, inv_tau, qxx, qyy, qxy, fs);
+      } else {
+        collide<C, TAU1>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
+      }
       const unsigned off = (unsigned)((y - 1) * pitch + col);
 #pragma unroll
       for (int i = 0; i < 9; ++i) ((GS*)(gout + i * plane))[off] = (S)fs[i];

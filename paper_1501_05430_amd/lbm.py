@@ -14,12 +14,18 @@ BOUNDARIES = {"walls": 0, "periodic": 1}
 
 def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=0, strip_rows=0,
                 enable_adjoint=False, step_variant=0, tau=1.0, G=-1.0, A=-0.6, eos_a=1.0, eos_b=4.0, eos_R=1.0, rho0_shift=0.0,
-                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls", piecewise=None):
+                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls", piecewise=None, mrt=None, kappa=0.0):
     """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'; boundary: 'walls'
     (ghost rows 0 and ny-1 with the geometric wetting) or 'periodic' (fluid rows 1..ny-2 wrap around).
     piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the piecewise-linear EOS of Eq. 11 (break points
-    from Eq. 12-13; T_over_Tc and eos_a/b/R are then unused); None selects Carnahan-Starling."""
+    from Eq. 12-13; T_over_Tc and eos_a/b/R are then unused); None selects Carnahan-Starling. mrt = (s_e, s_eps,
+    s_q) selects the MRT collision of Eq. 15 (0 entries mean 1/tau); kappa != 0 adds the surface-tension source of
+    Eq. 16-17 (and implies MRT)."""
     p = Params()
+    if mrt is not None:
+        for k in range(3):
+            p.mrt_rates[k] = float(mrt[k])
+    p.kappa = float(kappa)
     if piecewise is not None:
         p.eos = 1
         for k in range(3):

@@ -35,9 +35,10 @@ def test_binding_declares_every_entry_point():
 
 
 def test_params_struct_matches_header_size():
-    # lbm_params: 10 int32 + 16 double = 168 bytes, no padding
+    # lbm_params: 10 int32 + 20 double = 200 bytes, no padding
     from paper_1501_05430_amd import _lib
-    assert C.sizeof(_lib.Params) == 10 * 4 + 16 * 8
+    assert C.sizeof(_lib.Params) == 10 * 4 + 20 * 8
+    assert _lib.Params.kappa.offset == 10 * 4 + 19 * 8
     assert _lib.Params.pw_theta.offset == 10 * 4 + 11 * 8
 
 
@@ -60,6 +61,11 @@ def test_workspace_bytes_and_validation():
         dict(nx=20, ny=10, T_over_Tc=0.8, rho0_shift=0.3),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary=2),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary="periodic", enable_adjoint=True),
+        dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, 2.0, 1.0)),
+        dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, -0.5, 1.0)),
+        dict(nx=20, ny=10, T_over_Tc=0.8, kappa=float("nan")),
+        dict(nx=20, ny=10, T_over_Tc=0.8, kappa=0.5, enable_adjoint=True),
+        dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, 1.0, 1.0), enable_adjoint=True),
     ]
     for kw in bad:
         with pytest.raises(P.LbmError):
