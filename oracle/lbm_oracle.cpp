@@ -29,6 +29,11 @@
 //    rows 2 and ny-3 index 2. Ghost rows carry density and psi only. Populations use halfway bounce-back.
 //  * Ghost density: Eq. (19) when wet_iters == 0; otherwise the iteration of Eq. (21) with the square root of
 //    Eq. (20) restored, stopped after exactly wet_iters iterates (the first line of Eq. (21) is iterate 1).
+//  * Martys-Chen walls (wall_mode = 1, the method the paper compares against): the wall rows are solid nodes,
+//    S = 1 in Eq. (14), F_s = -G_w psi(x) sum_a w_a S(x + e_a) e_a with one G_w per wall. Solid nodes take no part
+//    in the fluid-fluid force or in Q (their psi is 0, as if absent); the paper does not say, and its G_w range
+//    (about -0.8 to -2.8 spanning 180 to 0 deg at a density ratio of 10) brackets -psi_v .. -psi_l, which fits
+//    walls that attract through F_s alone. No geometric wetting then.
 //  * Ghost density is clamped to [0, rho_cap (1 - 1e-6)], rho_cap the largest density with real psi (psi at the
 //    clamp is then ~1e-3, not a square root of round-off, so two independent rho_cap solves agree there);
 //    psi^2 is clamped at 0 on fluid nodes. Every clamp is counted.
@@ -90,6 +95,9 @@ typedef struct {
   int32_t pad2;
   double s_e, s_eps, s_q;  // Eq. (2): tau_e^-1, tau_xi^-1, tau_q^-1 (MRT only)
   double kappa;            // Eq. (17): surface-tension parameter (MRT only; 0 = no source C)
+  int32_t wall_mode;       // 0: geometric wetting (Sec. 4); 1: Martys-Chen fluid-solid force (Eq. 14)
+  int32_t pad3;
+  double G_w[2];           // Eq. (14): wall interaction strength of the bottom (row 0) and top (row ny-1) wall
 } ora_params;
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -431,6 +439,13 @@ struct Oracle {
     }
     cnt.psi_clamps += psi_clamps;
     if (p.periodic_y) return;
+    if (p.wall_mode == 1) {  // solid wall rows: absent from the fluid-fluid force
+      for (int x = 0; x < nx; ++x) {
+        rho[x] = psi[x] = S(0.0);
+        rho[(size_t)(ny - 1) * nx + x] = psi[(size_t)(ny - 1) * nx + x] = S(0.0);
+      }
+      return;
+    }
     // Ghost rows: bottom uses rows 1 (index 1) and 2 (index 2); top mirrors with rows ny-2 and ny-3.
     for (int wall = 0; wall < 2; ++wall) {
       int g = wall == 0 ? 0 : ny - 1;
@@ -465,6 +480,16 @@ struct Oracle {
     }
     *Fx = -p.A * su_x - (1.0 - p.A) * G_f * pc * sp_x;
     *Fy = -p.A * su_y - (1.0 - p.A) * G_f * pc * sp_y;
+    if (p.wall_mode == 1 && !p.periodic_y) {
+      // Eq. (14): F_s = -G_w psi(x) sum_a w_a S(x + e_a) e_a over the solid (wall-row) neighbours
+      for (int a = 1; a < 9; ++a) {
+        int yn = y + EY[a];
+        if (yn != 0 && yn != ny - 1) continue;
+        double gw = yn == 0 ? p.G_w[0] : p.G_w[1];
+        *Fx -= gw * pc * (WF[a] * (double)EX[a]);
+        *Fy -= gw * pc * (WF[a] * (double)EY[a]);
+      }
+    }
   }
 
   // Steps 5-6: collision with forcing at every fluid node, then streaming (halfway bounce-back at the walls).
@@ -571,6 +596,7 @@ bool params_ok(const ora_params* p) {
   if (!(p->tau > 0.5) || !(p->G < 0)) return false;
   if (p->mrt && !(p->s_e > 0 && p->s_e < 2 && p->s_eps > 0 && p->s_eps < 2 && p->s_q > 0 && p->s_q < 2)) return false;
   if (!p->mrt && p->kappa != 0.0) return false;
+  if (p->wall_mode != 0 && p->wall_mode != 1) return false;
   if (p->eos_kind == 1)
     return p->pw_theta_v > 0 && p->pw_theta_m < 0 && p->pw_theta_l > 0 && p->pw_rho1 > 0 && p->pw_rho2 > p->pw_rho1;
   return p->eos_kind == 0 && p->T > 0;

@@ -24,6 +24,7 @@ class OraParams(C.Structure):
         ("pw_rho1", C.c_double), ("pw_rho2", C.c_double),
         ("mrt", C.c_int32), ("pad2", C.c_int32),
         ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("kappa", C.c_double),
+        ("wall_mode", C.c_int32), ("pad3", C.c_int32), ("G_w", C.c_double * 2),
     ]
 
 
@@ -133,11 +134,12 @@ class Sim:
 
     def __init__(self, nx, ny, T_over_Tc, theta_bottom=np.pi / 2, theta_top=np.pi / 2, *, wet_iters=4, tau=1.0,
                  G=-1.0, A=-0.6, a=1.0, b=4.0, R=1.0, body_force=(0.0, 0.0), periodic_y=False, piecewise=None,
-                 mrt=None, kappa=0.0):
+                 mrt=None, kappa=0.0, G_w=None):
         """piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the EOS of Eq. (11) with the break points
         of Eq. (12)-(13) (T_over_Tc is then unused); None selects Carnahan-Starling. mrt = (s_e, s_eps, s_q) selects
         the MRT collision of Eq. (15) (the stress relaxes at 1/tau); kappa != 0 adds the source of Eq. (16)-(17) and
-        implies MRT (rates 1/tau where mrt is None)."""
+        implies MRT (rates 1/tau where mrt is None). G_w = (bottom, top) selects Martys-Chen walls (Eq. 14) in place
+        of the geometric wetting (the contact angles are then unused)."""
         if piecewise is None:
             rc, tc, pc = cs_critical(a, b, R)
             self.T_c = tc
@@ -152,6 +154,9 @@ class Sim:
             self.p.mrt = 1
             self.p.s_e, self.p.s_eps, self.p.s_q = (float(r) for r in rates)
             self.p.kappa = float(kappa)
+        if G_w is not None:
+            self.p.wall_mode = 1
+            self.p.G_w[0], self.p.G_w[1] = float(G_w[0]), float(G_w[1])
         if piecewise is not None:
             tv, tm, tl, rv, rl = piecewise
             r1, r2 = pw_breakpoints(tv, tm, tl, rv, rl)
