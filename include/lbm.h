@@ -55,8 +55,12 @@ typedef enum {
 
 typedef enum {
   LBM_WALLS_Y = 0,     /* rows 0 and ny-1 are the walls' ghost rows (Sec. 4 wetting, halfway bounce-back) */
-  LBM_PERIODIC_Y = 1   /* no walls: fluid rows 1..ny-2 wrap around (a periodic lattice of ny-2 rows; the ghost
-                          rows are unused and read back as 0). x is periodic in both cases. Forward only. */
+  LBM_PERIODIC_Y = 1,  /* no walls: fluid rows 1..ny-2 wrap around (a periodic lattice of ny-2 rows; the ghost
+                          rows are unused and read back as 0). x is periodic in all cases. Forward only. */
+  LBM_WALLS_MARTYS_CHEN = 2  /* the comparison method of Sec. 3: rows 0 and ny-1 are solid walls that attract the
+                          fluid through the force of Eq. 14 (strength G_w per wall) and take no part in the
+                          fluid-fluid force (psi = 0 there; they read back as 0); halfway bounce-back as for
+                          LBM_WALLS_Y, no geometric wetting (contact angles unused). Forward only. */
 } lbm_boundary;
 
 typedef enum {
@@ -102,6 +106,8 @@ typedef struct {
                              BGK, the same scheme up to rounding. Excludes enable_adjoint. [0, 0, 0] */
   double kappa;           /* surface-tension parameter of Eq. 16-17: the source C with Q = kappa (G/2)[...] scales
                              the surface tension by 1 - kappa and leaves flat-interface densities unchanged. [0] */
+  double G_w[2];          /* LBM_WALLS_MARTYS_CHEN: G_w of Eq. 14 for the bottom and top wall (more negative
+                             attracts more: smaller contact angle); ignored otherwise [0, 0] */
 } lbm_params;
 
 /* Device diagnostics of one instance, accumulated by the periodic checks (check_every) of lbm_step. */

@@ -20,6 +20,7 @@ class Params(C.Structure):
         ("rho0_shift", C.c_double), ("rho_fp64_below", C.c_double), ("body_force", C.c_double * 2),
         ("pw_theta", C.c_double * 3), ("pw_rho", C.c_double * 2),
         ("mrt_rates", C.c_double * 3), ("kappa", C.c_double),
+        ("G_w", C.c_double * 2),
     ]
 
 

@@ -225,7 +225,7 @@ constexpr bool kDefaultPrefetch64 = false;
 constexpr int kMinDefaultStripRows = 2;
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
-static_assert(sizeof(lbm_params) == 10 * 4 + 20 * 8, "lbm_params layout: 10 int32 then 20 double, no padding");
+static_assert(sizeof(lbm_params) == 10 * 4 + 22 * 8, "lbm_params layout: 10 int32 then 22 double, no padding");
 
 struct Inst {
   lbm_params p;
@@ -277,7 +277,10 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.check_every < 0) return bad("check_every < 0");
     if (q.strip_rows < 0) return bad("strip_rows < 0");
     if (q.step_variant < 0 || q.step_variant > 2 * kNumWaveChoices) return bad("step_variant outside [0, 8]");
-    if (q.boundary != LBM_WALLS_Y && q.boundary != LBM_PERIODIC_Y) return bad("unknown boundary");
+    if (q.boundary != LBM_WALLS_Y && q.boundary != LBM_PERIODIC_Y && q.boundary != LBM_WALLS_MARTYS_CHEN)
+      return bad("unknown boundary");
+    if (!std::isfinite(q.G_w[0]) || !std::isfinite(q.G_w[1])) return bad("G_w not finite");
+    if (q.boundary == LBM_WALLS_MARTYS_CHEN && q.enable_adjoint) return bad("the adjoint supports LBM_WALLS_Y only");
     if (q.eos != LBM_EOS_CARNAHAN_STARLING && q.eos != LBM_EOS_PIECEWISE_LINEAR) return bad("unknown eos");
     if (q.boundary == LBM_PERIODIC_Y && q.enable_adjoint) return bad("the adjoint supports LBM_WALLS_Y only");
     if ((int64_t)((q.nx + 63) / 64 * 64) * (q.ny - 2) * 9 >= ((int64_t)1 << 31)) return bad("lattice too large for 32-bit offsets");
@@ -518,6 +521,9 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     d.plane = I.plane;
     d.cur = 0;
     d.periodic_y = p[i].boundary == LBM_PERIODIC_Y ? 1 : 0;
+    d.wall_mc = p[i].boundary == LBM_WALLS_MARTYS_CHEN ? 1 : 0;
+    d.gw_half[0] = d.wall_mc ? 0.5 * p[i].G_w[0] : 0.0;
+    d.gw_half[1] = d.wall_mc ? 0.5 * p[i].G_w[1] : 0.0;
     d.RT = p[i].eos_R * I.T;
     d.eos_a = p[i].eos_a;
     d.eos_b4 = 0.25 * p[i].eos_b;

@@ -32,6 +32,8 @@ struct InstDesc {
   int32_t mrt, pad2;        // 1: MRT collision (Eq. 15) with the rates below, else BGK
   double s_e, s_eps, s_q;   // Eq. 2 relaxation rates (the stress relaxes at inv_tau)
   double kq;                // kappa G / 2 of Eq. 17 (0: no surface-tension source)
+  int32_t wall_mc, pad3;    // 1: Martys-Chen walls (Eq. 14): solid rows, psi = 0 there, no geometric wetting
+  double gw_half[2];        // G_w / 2 of the bottom and top wall
 };
 
 // One block's share of a step: columns [x0, x0+width) of rows [y0, y0+nrows) of instance inst

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   const int ylast = y0 + nrows - 1;
   const C rho0 = (C)d.rho0;
   const bool py = d.periodic_y != 0;  // rows wrap around, no walls
+  const bool mcw = d.wall_mc != 0;    // Martys-Chen walls: solid rows with the fluid-solid force of Eq. 14
   auto wrapy = [&](int y) { return y < 1 ? y + (ny - 2) : (y > ny - 2 ? y - (ny - 2) : y); };
 
   const int lx = wv * WAVE + lane;  // column offset inside the block
@@ -110,6 +111,10 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   // Ghost row beside wall `wall` (0 bottom, 1 top), Sec. 4: from the boundary row yb (densities r1, halo hr1) and
   // the second row (r2, halo hr2). Returns the ghost density and psi of the own column and the halo psi.
   auto ghost = [&](int wall, int yb, C r1, C r2, C hr1, C hr2, C& g_rho, C& g_psi, C& gh_psi) {
+    if (mcw) {  // solid wall rows (Eq. 14 mode): absent from the fluid-fluid force; uniform over the block
+      g_rho = g_psi = gh_psi = (C)0;
+      return;
+    }
     C L, R;
     xchg(r1, hr1, L, R);
     C ro = (C)0;
@@ -143,6 +148,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
   // MRT collision with the surface-tension source (never in the tau = 1 BGK specialisation)
   const bool mrt = !TAU1 && d.mrt != 0, kap = mrt && d.kq != 0.0;
   const C s_e = (C)d.s_e, s_eps = (C)d.s_eps, s_q = (C)d.s_q, kq = (C)d.kq;
+  const C gwb = (C)d.gw_half[0], gwt = (C)d.gw_half[1];  // G_w / 2 of the bottom and top wall
 
   // The strip's rows are walked upwards (DOWN = false) or downwards. Consecutive launches alternate, so each
   // launch first reads the rows that the previous one wrote last, while they are still in the memory-side cache.
@@ -222,6 +228,11 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
         const C suy = k1 * ((pn - pm) * (pn + pm)) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
         Fx = -Gf * ((C)0.5 * A * sux + ((C)1 - A) * pc * spx) + bfx;
         Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
+        // Eq. 14 next to a flat solid row: sum_a w_a S(x + e_a) e_a = (0, -1/2) below, (0, 1/2) above
+        if (mcw) {
+          if (y == 1) Fy = Fy + gwb * pc;
+          if (y == ny - 2) Fy = Fy - gwt * pc;
+        }
       }
       C fs[9];
       if (mrt) {
@@ -411,7 +422,7 @@ __global__ __launch_bounds__(BLOCK) void k_wetting(const InstDesc* __restrict__ 
   const int t = (int)(blockIdx.x * BLOCK + threadIdx.x);
   if (t >= 2 * nx) return;
   const int wall = t / nx, x = t % nx;
-  if (d.periodic_y) {  // no walls
+  if (d.periodic_y || d.wall_mc) {  // no walls, or solid walls without ghost densities
     d.ghost[wall * nx + x] = 0.0;
     return;
   }

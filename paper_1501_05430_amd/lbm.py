@@ -9,14 +9,16 @@ from . import _lib
 from ._lib import LbmError, Params, check, PRECISIONS
 
 
-BOUNDARIES = {"walls": 0, "periodic": 1}
+BOUNDARIES = {"walls": 0, "periodic": 1, "martys_chen": 2}
 
 
 def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=0, strip_rows=0,
                 enable_adjoint=False, step_variant=0, tau=1.0, G=-1.0, A=-0.6, eos_a=1.0, eos_b=4.0, eos_R=1.0, rho0_shift=0.0,
-                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls", piecewise=None, mrt=None, kappa=0.0):
+                rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls", piecewise=None, mrt=None, kappa=0.0,
+                G_w=(0.0, 0.0)):
     """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'; boundary: 'walls'
-    (ghost rows 0 and ny-1 with the geometric wetting) or 'periodic' (fluid rows 1..ny-2 wrap around).
+    (ghost rows 0 and ny-1 with the geometric wetting), 'periodic' (fluid rows 1..ny-2 wrap around) or
+    'martys_chen' (solid walls with the fluid-solid force of Eq. 14, strengths G_w = (bottom, top)).
     piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the piecewise-linear EOS of Eq. 11 (break points
     from Eq. 12-13; T_over_Tc and eos_a/b/R are then unused); None selects Carnahan-Starling. mrt = (s_e, s_eps,
     s_q) selects the MRT collision of Eq. 15 (0 entries mean 1/tau); kappa != 0 adds the surface-tension source of
@@ -26,6 +28,7 @@ def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=
         for k in range(3):
             p.mrt_rates[k] = float(mrt[k])
     p.kappa = float(kappa)
+    p.G_w[0], p.G_w[1] = float(G_w[0]), float(G_w[1])
     if piecewise is not None:
         p.eos = 1
         for k in range(3):

@@ -35,10 +35,11 @@ def test_binding_declares_every_entry_point():
 
 
 def test_params_struct_matches_header_size():
-    # lbm_params: 10 int32 + 20 double = 200 bytes, no padding
+    # lbm_params: 10 int32 + 22 double = 216 bytes, no padding
     from paper_1501_05430_amd import _lib
-    assert C.sizeof(_lib.Params) == 10 * 4 + 20 * 8
+    assert C.sizeof(_lib.Params) == 10 * 4 + 22 * 8
     assert _lib.Params.kappa.offset == 10 * 4 + 19 * 8
+    assert _lib.Params.G_w.offset == 10 * 4 + 20 * 8
     assert _lib.Params.pw_theta.offset == 10 * 4 + 11 * 8
 
 
@@ -59,7 +60,9 @@ def test_workspace_bytes_and_validation():
         dict(nx=20, ny=10, T_over_Tc=0.8, wet_iters=-1),
         dict(nx=20, ny=10, T_over_Tc=0.8, step_variant=9),
         dict(nx=20, ny=10, T_over_Tc=0.8, rho0_shift=0.3),
-        dict(nx=20, ny=10, T_over_Tc=0.8, boundary=2),
+        dict(nx=20, ny=10, T_over_Tc=0.8, boundary=3),
+        dict(nx=20, ny=10, T_over_Tc=0.8, boundary="martys_chen", enable_adjoint=True),
+        dict(nx=20, ny=10, T_over_Tc=0.8, boundary="martys_chen", G_w=(float("inf"), -1.0)),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary="periodic", enable_adjoint=True),
         dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, 2.0, 1.0)),
         dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, -0.5, 1.0)),

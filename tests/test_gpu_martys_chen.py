@@ -1,0 +1,141 @@
+"""Martys-Chen walls (Eq. 14, the comparison method of Sec. 3) through the C-ABI: FP64 steps against the CPU
+reference (Carnahan-Starling and the Table 1 EOS, with the surface-tension source and MRT rates, different G_w on
+the two walls), an FP32 slice, and the rest state that the matching G_w keeps exactly."""
+import numpy as np
+import pytest
+
+from gpu_helpers import oracle_pops
+
+pytestmark = pytest.mark.gpu
+
+PW = {10: (0.25, -0.02, 0.3, 1.0, 10.0), 100: (0.1633, -0.02, 0.33333, 1.0, 100.0)}
+
+CASES = {
+    "cs085": (0.85, None, dict(G_w=(-0.3, -0.3))),
+    "cs085_asym_tau08": (0.85, None, dict(G_w=(-0.35, -0.2), A=-0.3, tau=0.8)),
+    "cs085_asym_sc": (0.85, None, dict(G_w=(-0.3, -0.2), A=0.0)),
+    "pw10_k05": (1.0, 10, dict(G_w=(-1.5, -1.5), kappa=0.5)),        # Sec. 3.1's setting at a ratio of 10
+    "pw10_k05_strong": (1.0, 10, dict(G_w=(-2.5, -1.0), kappa=0.5)),
+    "pw10_mrt_gravity": (1.0, 10, dict(G_w=(-1.2, -1.8), tau=0.9, mrt=(1.2, 1.4, 1.1), body_force=(0.0, -1e-5))),
+    "pw100_k05": (1.0, 100, dict(G_w=(-3.5, -3.5), kappa=0.5)),
+}
+
+
+def pair(ora, T, ratio, kw, nx=200, ny=100, precision="f64", R=30.0):
+    import paper_1501_05430_amd as P
+    pw = PW[ratio] if ratio else None
+    ref = ora.Sim(nx, ny, T, piecewise=pw, **kw)
+    ref.init_droplets([nx / 2], [0.5], [R])
+    sim = P.LBM(P.make_params(nx, ny, T, precision=precision, piecewise=pw, boundary="martys_chen",
+                              **P.fp32_options(T, precision, piecewise=pw), **kw))
+    sim.init_droplet(nx / 2, 0.5, R)
+    return ref, sim
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_wall_droplet_fp64_matches_reference(ora, name):
+    T, ratio, kw = CASES[name]
+    ref, sim = pair(ora, T, ratio, kw)
+    for n in (1, 299):
+        ref.run(n)
+        sim.step(n)
+        f_ref = oracle_pops(ref)
+        err = np.abs(sim.populations() - f_ref).max() / np.abs(f_ref).max()
+        assert err <= 1e-12, (n, err)
+    r = sim.rho()
+    assert np.all(r[0] == 0) and np.all(r[-1] == 0)
+    assert sim.mass() == pytest.approx(ref.mass(), rel=1e-12)
+    sim.close()
+
+
+def test_fp32_shifted_slice(ora):
+    T, ratio, kw = CASES["pw10_k05"]
+    ref, sim = pair(ora, T, ratio, kw, precision="f32_shifted")
+    ref.run(100)
+    sim.step(100)
+    r_ref, _ = ref.density()
+    err = np.abs(sim.rho()[1:-1] - r_ref[1:-1]).max() / PW[10][4]
+    sim.close()
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("A", [0.0, -0.6])
+def test_rest_state_kept_at_the_matching_G_w(ora, A):
+    """Uniform fluid at rest: G_w = G psi (1 - A/2) cancels the wall neighbours missing from Eq. 9 exactly."""
+    import paper_1501_05430_amd as P
+    rho = 0.05
+    gw = -ora.psi(ora.Sim(4, 4, 0.85, A=A), rho) * (1 - A / 2)
+    sim = P.LBM(P.make_params(70, 12, 0.85, A=A, boundary="martys_chen", G_w=(gw, gw)))
+    sim.init_droplet([], [], [], rho_v=rho, rho_l=rho)
+    f0 = sim.populations()
+    sim.step(100)
+    err = np.abs(sim.populations() - f0).max() / rho
+    sim.close()
+    assert err <= 1e-14, err
+
+
+def sec31_run(ratio, gw, steps=60000):
+    """Sec. 3.1's setup with Martys-Chen walls: Table 1 EOS, kappa = 0.5, A = -0.6, Lambda = diag(0,1,...,1),
+    semicircle R = 30 on the bottom wall of a 200 x 100 lattice (G_w on the bottom wall; the top wall without
+    fluid-solid force, G_w = 0). Returns (stable, theta in degrees or None, density)."""
+    import math
+    import paper_1501_05430_amd as P
+    pw = {10: PW[10], 100: PW[100], 1000: (0.2, -0.01, 0.33333, 1.0, 1000.0)}[ratio]
+    sim = P.LBM(P.make_params(200, 100, 1.0, piecewise=pw, kappa=0.5, boundary="martys_chen", G_w=(gw, 0.0),
+                              check_every=500))
+    sim.init_droplet(100.0, 0.5, 30.0)
+    try:
+        sim.step(steps)
+    except P.LbmError as e:
+        assert e.code == 4   # non-finite density detected by the periodic check
+        sim.close()
+        return False, None, None
+    th = math.degrees(sim.measure_contact_angle((0, 200, 1, 80), 0)[0])
+    r = sim.rho()
+    sim.close()
+    return True, th, r
+
+
+def test_sec3_contact_angle_range_at_density_ratio_10():
+    """Fig. 1: with G_w from -0.766 to -2.766 the contact angle covers most of 0-180 deg. Measured: 180, 138.3,
+    113.1, 93.6, 77.3, 61.2, 45.6, 32.9 deg for G_w = -0.766, -1.0, -1.3, ..., -2.766."""
+    gws = (-0.766, -1.0, -1.3, -1.6, -1.9, -2.2, -2.5, -2.766)
+    th = []
+    for gw in gws:
+        ok, t, _ = sec31_run(10, gw)
+        assert ok, gw
+        th.append(t)
+    assert all(a > b for a, b in zip(th, th[1:])), th        # more negative G_w wets more
+    assert th[0] > 170 and th[-1] < 40, th
+
+
+def test_sec3_stability_limits_at_density_ratios_100_and_1000():
+    """Fig. 2 and Sec. 3.1: at a ratio of 100 the method stays stable only down to a G_w whose angle is still
+    obtuse (measured: -3.5 gives 113.7 deg, -4.0 diverges; the paper reaches about 90 deg at -4); at a ratio of
+    1000 a G_w weak enough to be stable leaves the droplet unattached (180 deg) and one strong enough to attach it
+    diverges."""
+    ok, t, _ = sec31_run(100, -3.5)
+    assert ok and 95 < t < 130, t
+    ok, _, _ = sec31_run(100, -4.5)
+    assert not ok
+    ok, t, _ = sec31_run(1000, -3.0)
+    assert ok and t > 175, t
+    ok, _, _ = sec31_run(1000, -5.0)
+    assert not ok
+
+
+def test_sec3_near_wall_density_distortion():
+    """Fig. 3: the fluid-solid force condenses the vapour next to the wall (boundary-row vapour density about twice
+    the bulk at G_w = -1.6, 94 deg), while the geometric wall leaves it at the bulk value (to 1e-3)."""
+    import math
+    import paper_1501_05430_amd as P
+    ok, t, r = sec31_run(10, -1.6)
+    assert ok
+    assert r[1, 0] > 1.5 * r[50, 0], (r[1, 0], r[50, 0])
+    sim = P.LBM(P.make_params(200, 100, 1.0, piecewise=PW[10], kappa=0.5, check_every=500))
+    sim.apply_wetting(math.radians(60.0), math.pi / 2)
+    sim.init_droplet(100.0, 0.5, 30.0)
+    sim.step(60000)
+    r = sim.rho()
+    sim.close()
+    assert abs(r[1, 0] - r[50, 0]) <= 1e-3 * r[50, 0], (r[1, 0], r[50, 0])
