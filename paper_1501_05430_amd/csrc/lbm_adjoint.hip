@@ -27,7 +27,7 @@ namespace lbm {
 namespace {
 
 constexpr int AB = 256;          // block size
-constexpr int kAdjBlocks = 1024; // grid of the reductions (grid-stride)
+constexpr int kAdjBlocks = 4096; // largest grid of the passes that leave reduction partials (grid-stride)
 
 __device__ inline double dp_drho(const InstDesc& d, double rho) {
   // Eq. 11: the slope of the segment that the forward pass evaluated (same comparisons)
@@ -112,65 +112,56 @@ __device__ inline void force_at(const InstDesc& d, const Field& P, int nx, int x
   Fy = -Gf * (0.5 * A * suy + (1.0 - A) * pc * spy);
 }
 
-// 2. streaming and collision transposed; writes the direct part of lambda_n and F_bar; partials of G_f_bar
-__global__ __launch_bounds__(AB) void ka_collide(const InstDesc* __restrict__ descs, int inst,
-                                                 const double* __restrict__ f, const double* __restrict__ lam1,
-                                                 double* __restrict__ lam0, AdjScratch sc) {
-  __shared__ double sm[AB / 64];
-  const InstDesc& d = descs[inst];
-  const int nx = d.nx, ny = d.ny;
-  const int64_t n = (int64_t)nx * (ny - 2);
-  Field P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
-  double gf_part = 0.0;
-  for (unsigned k = blockIdx.x * AB + threadIdx.x; k < (unsigned)n; k += gridDim.x * AB) {
-    const int x = (int)(k % (unsigned)nx), y = (int)(k / (unsigned)nx) + 1;
-    double fl[9], ls[9];
+// 2. streaming and collision transposed at fluid node (x, y): the direct part of lambda_n (lam), F_bar, and the
+//    interaction force F_i (for G_f_bar = F_bar . F_i / G_f).
+// Loads of node (x, y): its populations f and the streamed-back adjoint lambda*_i = lambda_i(x + e_i) (or
+// lambda_{opp(i)}(x) where x + e_i is a ghost row).
+__device__ inline void adj_loads(const double* __restrict__ f, const double* __restrict__ lam1, int64_t n, int nx,
+                                 int ny, int x, int y, double (&fl)[9], double (&ls)[9]) {
+  const unsigned k = (unsigned)((y - 1) * nx + x);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      fl[i] = f[i * n + k];
-      const int yd = y + kEY[i];
-      ls[i] = (yd < 1 || yd > ny - 2) ? lam1[kOPP[i] * n + k]
-                                      : lam1[i * n + (int64_t)(yd - 1) * nx + wrapx(x + kEX[i], nx)];
-    }
-    double Fix, Fiy;
-    force_at(d, P, nx, x, y, Fix, Fiy);
-    const double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
-    // forward collision quantities
-    const double rho = sum9(fl);
-    const double jx = mom_x(fl), jy = mom_y(fl);
-    const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
-    const double v2 = vx * vx + vy * vy;
-    const double it = d.inv_tau, pref = d.force_pref;
-    double rhob = 0.0, vbx = 0.0, vby = 0.0, Fbx = 0.0, Fby = 0.0;
-    double fb[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const double ex = kEX[i], ey = kEY[i], w = kW[i];
-      const double eu = ex * vx + ey * vy, eF = ex * Fx + ey * Fy;
-      fb[i] = (1.0 - it) * ls[i];
-      const double q = ls[i] * it;  // adjoint of f_eq_i
-      rhob += q * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
-      vbx += q * w * rho * (3.0 * ex + 9.0 * eu * ex - 3.0 * vx);
-      vby += q * w * rho * (3.0 * ey + 9.0 * eu * ey - 3.0 * vy);
-      const double s = ls[i] * pref * w;  // adjoint of the forcing term / (pref w)
-      vbx += s * (-3.0 * Fx + 9.0 * eF * ex);
-      vby += s * (-3.0 * Fy + 9.0 * eF * ey);
-      Fbx += s * (3.0 * ex - 3.0 * vx + 9.0 * eu * ex);
-      Fby += s * (3.0 * ey - 3.0 * vy + 9.0 * eu * ey);
-    }
-    // v = (j + F/2) / rho
-    const double jbx = vbx / rho, jby = vby / rho;
-    Fbx += 0.5 * vbx / rho;
-    Fby += 0.5 * vby / rho;
-    rhob -= (vbx * vx + vby * vy) / rho;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) lam0[i * n + k] = fb[i] + rhob + jbx * kEX[i] + jby * kEY[i];
-    FX.at(x, y) = Fbx;
-    FY.at(x, y) = Fby;
-    gf_part += (Fbx * Fix + Fby * Fiy) / d.G_f;
+  for (int i = 0; i < 9; ++i) {
+    fl[i] = f[i * n + k];
+    const int yd = y + kEY[i];
+    ls[i] = (yd < 1 || yd > ny - 2) ? lam1[kOPP[i] * n + k]
+                                    : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))];
   }
-  const double t = block_sum(gf_part, sm);
-  if (threadIdx.x == 0) sc.part[blockIdx.x] = t;
+}
+
+__device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fix,
+                                   double Fiy, double (&lam)[9], double& Fbx, double& Fby) {
+  const double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
+  // forward collision quantities
+  const double rho = sum9(fl);
+  const double jx = mom_x(fl), jy = mom_y(fl);
+  const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
+  const double v2 = vx * vx + vy * vy;
+  const double it = d.inv_tau, pref = d.force_pref;
+  double rhob = 0.0, vbx = 0.0, vby = 0.0;
+  Fbx = 0.0;
+  Fby = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double ex = kEX[i], ey = kEY[i], w = kW[i];
+    const double eu = ex * vx + ey * vy, eF = ex * Fx + ey * Fy;
+    lam[i] = (1.0 - it) * ls[i];
+    const double q = ls[i] * it;  // adjoint of f_eq_i
+    rhob += q * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
+    vbx += q * w * rho * (3.0 * ex + 9.0 * eu * ex - 3.0 * vx);
+    vby += q * w * rho * (3.0 * ey + 9.0 * eu * ey - 3.0 * vy);
+    const double s = ls[i] * pref * w;  // adjoint of the forcing term / (pref w)
+    vbx += s * (-3.0 * Fx + 9.0 * eF * ex);
+    vby += s * (-3.0 * Fy + 9.0 * eF * ey);
+    Fbx += s * (3.0 * ex - 3.0 * vx + 9.0 * eu * ex);
+    Fby += s * (3.0 * ey - 3.0 * vy + 9.0 * eu * ey);
+  }
+  // v = (j + F/2) / rho
+  const double jbx = vbx / rho, jby = vby / rho;
+  Fbx += 0.5 * vbx / rho;
+  Fby += 0.5 * vby / rho;
+  rhob -= (vbx * vx + vby * vy) / rho;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lam[i] += rhob + jbx * kEX[i] + jby * kEY[i];
 }
 
 // psi_bar at node y from the force of node x = y - e_a (x a fluid node): -G_f w_a (F_bar(x).e_a)(A psi(y) + (1-A) psi(x))
@@ -256,42 +247,202 @@ __global__ __launch_bounds__(AB) void ka_ghost_adj(const InstDesc* __restrict__ 
   if (threadIdx.x == 0) sc.part[kAdjBlocks + blockIdx.x] = tot;
 }
 
-// 5. psi transposed at fluid nodes (own force and the neighbours' forces), plus the wetting's boundary-row
-//    adjoints; lambda_n += rho_bar; partials of G_psi_bar.
-__global__ __launch_bounds__(AB) void ka_psi(const InstDesc* __restrict__ descs, int inst, double* __restrict__ lam0,
-                                             AdjScratch sc) {
-  __shared__ double sm[AB / 64];
+// 3 + 5 fused: one wavefront walks a strip of rows [y0, ylast] over at most 62 columns. Row by row it transposes
+// the streaming and collision one row ahead (stage C, also on one halo column at each side and on the rows y0 - 1
+// and ylast + 1), keeps that row's F_bar in a ring of three rows in LDS, and transposes the force and psi for the
+// row behind (stage S): psi_bar from its own force and the eight neighbours' forces, rho_bar = psi_bar dpsi/drho,
+// and lambda_n = direct part + rho_bar, written once. psi stays in a window of four rows in registers (neighbour
+// columns by lane shuffles; the two edge lanes also hold the next column out), and every global load of a row
+// iteration is for a later row (populations and lambda_{n+1} of the next stage C row, psi two rows ahead, rho of
+// the next stage S row), so it is in flight while the current rows are computed. F_bar of the boundary rows 1 and
+// ny-2 also goes to the scratch for the ghost rows' adjoint, whose boundary-row terms ka_wall_fix adds afterwards.
+// Partials of G_f_bar (stage C) and G_psi_bar (stage S) per block, over the block's own columns and rows only.
+constexpr int FL = 64;         // lanes per block (one wavefront): at most 62 own columns, one halo column each side
+
+// Interaction force (Eq. 9) from the 3 x 3 psi values around the node: rows below (m), own (c), above (n).
+__device__ inline void force_vals(const InstDesc& d, double pmL, double pm, double pmR, double pcL, double pcR,
+                                  double pc, double pnL, double pn, double pnR, double& Fx, double& Fy) {
+  const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, A = d.A, Gf = d.G_f;
+  const double spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
+  const double spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
+  const double sux = k1 * (pcR * pcR - pcL * pcL) + k2 * ((pnR * pnR - pnL * pnL) + (pmR * pmR - pmL * pmL));
+  const double suy = k1 * (pn * pn - pm * pm) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
+  Fx = -Gf * (0.5 * A * sux + (1.0 - A) * pc * spx);
+  Fy = -Gf * (0.5 * A * suy + (1.0 - A) * pc * spy);
+}
+
+__global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
+                                               const double* __restrict__ f, const double* __restrict__ lam1,
+                                               double* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
+                                               int ntasks) {
+  __shared__ double ring[3][2][FL];
+  __shared__ double ldir[9][FL];  // direct part of lambda_n of the stage C row, read back by the next stage S
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int64_t n = (int64_t)nx * (ny - 2);
   Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
-  double gpsi = 0.0;
-  for (unsigned k = blockIdx.x * AB + threadIdx.x; k < (unsigned)n; k += gridDim.x * AB) {
-    const int x = (int)(k % (unsigned)nx), y = (int)(k / (unsigned)nx) + 1;
-    const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
-    // own force: d F(x) / d psi(x) = -G_f (1 - A) sum_a w_a psi(x + e_a) e_a
-    const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0;
-    const double spx = k1 * (P.at(xr, y) - P.at(xl, y)) + k2 * ((P.at(xr, y + 1) - P.at(xl, y + 1)) +
-                                                               (P.at(xr, y - 1) - P.at(xl, y - 1)));
-    const double spy = k1 * (P.at(x, y + 1) - P.at(x, y - 1)) + k2 * ((P.at(xr, y + 1) + P.at(xl, y + 1)) -
-                                                                     (P.at(xr, y - 1) + P.at(xl, y - 1)));
-    double pb = -d.G_f * (1.0 - d.A) * (FX.at(x, y) * spx + FY.at(x, y) * spy);
-    pb += psi_bar_from(d, P, FX, FY, nx, ny, x, y);
-    const double psi = P.at(x, y), rho = R.at(x, y);
-    if (psi > 0.0) gpsi += pb * (-psi * 0.5 * d.two_over_Gpsi * 0.5);
-    double rb = pb * dpsi_drho(d, rho, psi);
-    // boundary-row densities feed the ghost rows (bottom: rows 1, 2; top: rows ny-2, ny-3)
-    for (int wall = 0; wall < 2; ++wall) {
-      const int r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
-      const double* wet = sc.wet + wall * 4 * nx;
-      if (y == r1) rb += wet[2 * nx + x] + wet[0 * nx + xr] + wet[1 * nx + xl];
-      if (y == r2) rb += wet[3 * nx + x];
-    }
+  const int l = (int)threadIdx.x;
+  const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, Gf = d.G_f, A = d.A;
+  double gf_part = 0.0, gpsi = 0.0;
+  for (int t = (int)blockIdx.x; t < ntasks; t += (int)gridDim.x) {
+    const int cb = t % ncb, sb = t / ncb;
+    const int x0 = cb * bw, w = min(bw, nx - x0);
+    const int y0 = 1 + sb * H, ylast = min(ny - 2, y0 + H - 1);
+    const bool act = l <= w + 1;          // lanes 0 .. w+1: columns x0-1 .. x0+w
+    const bool own = l >= 1 && l <= w;    // lanes 1 .. w: the block's own columns
+    const bool ledge = l == 0, redge = l == w + 1;
+    const int x = act ? wrapx(x0 - 1 + l, nx) : 0;
+    const int xo = ledge ? wrapx(x - 1, nx) : wrapx(x + 1, nx);  // next column out (edge lanes only)
+    const int yc0 = max(1, y0 - 1), yc1 = min(ny - 2, ylast + 1);
+    // psi window: rows yc-2 (a), yc-1 (b), yc (c), yc+1 (e) at the stage C row yc; o* = the edge lanes' outer column
+    double pa = 0.0, pb = 0.0, pc = 0.0, pe = 0.0, oa = 0.0, ob = 0.0, oc = 0.0, oe = 0.0;
+    auto psi_row = [&](int y, double& v, double& o) {
+      v = act ? P.at(x, y) : 0.0;
+      o = (ledge || redge) ? P.at(xo, y) : 0.0;
+    };
+    psi_row(yc0 - 1, pb, ob);
+    psi_row(yc0, pc, oc);
+    psi_row(yc0 + 1, pe, oe);
+    double lcur[9], flc[9], lsc[9], fln[9], lsn[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lam0[i * n + k] += rb;
+    for (int i = 0; i < 9; ++i) lcur[i] = fln[i] = lsn[i] = flc[i] = lsc[i] = 0.0;
+    if (act) adj_loads(f, lam1, n, nx, ny, x, yc0, flc, lsc);
+    double rho_s = act ? R.at(x, yc0) : 0.0;   // rho of the next stage S row (yc0 - 1 is never one)
+    // left / right neighbours of a per-lane value (the edge lanes take the outer column)
+    auto lr = [&](double v, double o, double& L, double& Rr) {
+      const double sl = __shfl(v, l > 0 ? l - 1 : 0, FL), sr = __shfl(v, l < FL - 1 ? l + 1 : FL - 1, FL);
+      L = ledge ? o : sl;
+      Rr = redge ? o : sr;
+    };
+    for (int yc = yc0; yc <= yc1; ++yc) {
+      // loads for later rows first
+      double pnext = 0.0, onext = 0.0, rho_next = 0.0;
+      if (act && yc < yc1) adj_loads(f, lam1, n, nx, ny, x, yc + 1, fln, lsn);
+      if (yc + 2 <= ny - 1) psi_row(yc + 2, pnext, onext);
+      if (act) rho_next = R.at(x, yc);
+      // stage C at row yc
+      double bL, bR, cL, cR, eL, eR;
+      lr(pb, ob, bL, bR);
+      lr(pc, oc, cL, cR);
+      lr(pe, oe, eL, eR);
+      double Fbx = 0.0, Fby = 0.0;
+      if (act) {
+        double Fix, Fiy;
+        force_vals(d, bL, pb, bR, cL, cR, pc, eL, pe, eR, Fix, Fiy);
+        collide_adj(d, flc, lsc, Fix, Fiy, lcur, Fbx, Fby);
+        if (own) {
+          if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) / Gf;  // halo rows belong elsewhere
+          if (yc == 1 || yc == ny - 2) {
+            FX.at(x, yc) = Fbx;
+            FY.at(x, yc) = Fby;
+          }
+        }
+      }
+      __syncthreads();  // the slot written next was read by stage S two rows back
+      ring[yc % 3][0][l] = Fbx;
+      ring[yc % 3][1][l] = Fby;
+      __syncthreads();
+      // stage S at row ys = yc - 1 from psi rows yc-2 (m), yc-1 (c), yc (n)
+      const int ys = yc - 1;
+      if (ys >= y0 && ys <= ylast) {
+        double aL, aR;
+        lr(pa, oa, aL, aR);
+        if (own) {
+          const double pv[3][3] = {{aL, pa, aR}, {bL, pb, bR}, {cL, pc, cR}};  // [row ys-1..ys+1][x-1..x+1]
+          const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
+          const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
+          double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
+#pragma unroll
+          for (int q = 1; q < 9; ++q) {
+            const int yn = ys - kEY[q];
+            if (yn < 1 || yn > ny - 2) continue;
+            const int ln = l - kEX[q], slot = yn % 3;
+            const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+            const double fe = ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q];
+            acc += -Gf * wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
+          }
+          if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
+          const double rb = acc * dpsi_drho(d, rho_s, pb);
+          const unsigned k = (unsigned)((ys - 1) * nx + x);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rb;
+        }
+      }
+      // slide: rows move down the window, the loads above become the current ones
+      pa = pb; pb = pc; pc = pe; pe = pnext;
+      oa = ob; ob = oc; oc = oe; oe = onext;
+      rho_s = rho_next;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        ldir[i][l] = lcur[i];  // same lane reads it back at the next stage S
+        flc[i] = fln[i];
+        lsc[i] = lsn[i];
+      }
+    }
+    // the top wall's boundary row: no stage C row above it (row ny-1 is the ghost row, F_bar absent there)
+    if (ylast == ny - 2) {
+      const int ys = ylast;  // window after the slide: pa = row ys-1, pb = row ys, pc = row ys+1 (ghost)
+      double aL, aR, bL, bR, cL, cR;
+      lr(pa, oa, aL, aR);
+      lr(pb, ob, bL, bR);
+      lr(pc, oc, cL, cR);
+      if (own) {
+        const double pv[3][3] = {{aL, pa, aR}, {bL, pb, bR}, {cL, pc, cR}};
+        const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
+        const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
+        double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+          const int yn = ys - kEY[q];
+          if (yn < 1 || yn > ny - 2) continue;
+          const int ln = l - kEX[q], slot = yn % 3;
+          const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+          const double fe = ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q];
+          acc += -Gf * wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
+        }
+        if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
+        const double rb = acc * dpsi_drho(d, rho_s, pb);
+        const unsigned k = (unsigned)((ys - 1) * nx + x);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rb;
+      }
+    }
+    __syncthreads();  // the ring is reused by the next task
   }
-  const double tot = block_sum(gpsi, sm);
-  if (threadIdx.x == 0) sc.part[2 * kAdjBlocks + blockIdx.x] = tot;
+  const double tf = wave_sum(gf_part);  // one wavefront per block
+  const double tp = wave_sum(gpsi);
+  if (threadIdx.x == 0) {
+    sc.part[blockIdx.x] = tf;
+    sc.part[2 * kAdjBlocks + blockIdx.x] = tp;
+  }
+}
+
+// The wetting's boundary-row adjoints (from ka_ghost_adj) into lambda_n: rows 1, 2 (bottom wall) and ny-2, ny-3
+// (top wall), each fluid row once, every population of the node (rho = sum_i f_i).
+__global__ __launch_bounds__(AB) void ka_wall_fix(const InstDesc* __restrict__ descs, int inst,
+                                                  double* __restrict__ lam0, AdjScratch sc) {
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  const int64_t n = (int64_t)nx * (ny - 2);
+  const int t = (int)(blockIdx.x * AB + threadIdx.x);
+  if (t >= 4 * nx) return;
+  const int j = t / nx, x = t % nx;
+  const int rows[4] = {1, 2, ny - 3, ny - 2};
+  const int y = rows[j];
+  for (int m = 0; m < j; ++m)
+    if (rows[m] == y) return;  // a row listed twice (ny < 6) is handled by its first entry
+  if (y < 1 || y > ny - 2) return;
+  const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
+  double rb = 0.0;
+  for (int wall = 0; wall < 2; ++wall) {
+    const int r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
+    const double* wet = sc.wet + wall * 4 * nx;
+    if (y == r1) rb += wet[2 * nx + x] + wet[0 * nx + xr] + wet[1 * nx + xl];
+    if (y == r2) rb += wet[3 * nx + x];
+  }
+  const unsigned k = (unsigned)((y - 1) * nx + x);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lam0[i * n + k] += rb;
 }
 
 // Fold of the partials into G_bar by one block: each thread sums a fixed strided subset in order, then a fixed
@@ -324,13 +475,29 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
   const unsigned gprep = (unsigned)((n + AB - 1) / AB);
   const unsigned gghost = (unsigned)((2 * h.nx + AB - 1) / AB);
   if (gghost > (unsigned)kAdjBlocks) return hipErrorInvalidValue;
-  const unsigned gred = (unsigned)std::min<int64_t>(kAdjBlocks, (n + AB - 1) / AB);
+  // fused pass: column blocks of at most FL - 2 columns (balanced), and row strips sized so that the tasks fit
+  // in one round of resident wavefronts (eight per compute unit at this kernel's register use), at least 4 rows
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ? v : 256;
+  }
+  const int ncb = (h.nx + FL - 3) / (FL - 2);
+  const int bw = (h.nx + ncb - 1) / ncb;
+  const int nyf = h.ny - 2;
+  const int strips = std::max(1, std::min(nyf, 8 * cus / ncb));
+  const int H = std::max(4, (nyf + strips - 1) / strips);
+  const int ntasks = ncb * ((nyf + H - 1) / H);
+  const unsigned gfused = (unsigned)std::min(ntasks, kAdjBlocks);
   hipLaunchKernelGGL(ka_prep, dim3(gprep), dim3(AB), 0, s, d_desc, inst, f_n, sc);
   hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
-  hipLaunchKernelGGL(ka_collide, dim3(gred), dim3(AB), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc);
+  hipLaunchKernelGGL(ka_fused, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb, H,
+                     ntasks);
   hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
-  hipLaunchKernelGGL(ka_psi, dim3(gred), dim3(AB), 0, s, d_desc, inst, lam_n, sc);
-  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(AB), 0, s, sc, (int)gred, (int)gghost, G_bar);
+  hipLaunchKernelGGL(ka_wall_fix, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, lam_n,
+                     sc);
+  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(AB), 0, s, sc, (int)gfused, (int)gghost, G_bar);
   return hipGetLastError();
 }
 
