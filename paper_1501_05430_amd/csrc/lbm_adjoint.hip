@@ -62,22 +62,39 @@ __device__ inline double block_sum(double v, double* sm) {
   return t;
 }
 
-// 1. forward densities and psi at fluid nodes (physical populations f, [9][ny-2][nx])
-__global__ __launch_bounds__(AB) void ka_prep(const InstDesc* __restrict__ descs, int inst, const double* __restrict__ f,
-                                              AdjScratch sc) {
-  const InstDesc& d = descs[inst];
-  const int nx = d.nx, ny = d.ny;
-  const int64_t n = (int64_t)nx * (ny - 2);
-  const unsigned k = blockIdx.x * AB + threadIdx.x;  // node counts are below 2^31 (lbm_create checks)
-  if (k >= (unsigned)n) return;
-  const int x = (int)(k % (unsigned)nx), y = (int)(k / (unsigned)nx) + 1;
-  double r = f[k];
+// 1. forward density and psi of a fluid node from its populations (summed in index order; every pass uses this)
+__device__ inline void node_rho_psi(const InstDesc& d, const double (&fl)[9], double& r, double& p) {
+  r = fl[0];
 #pragma unroll
-  for (int i = 1; i < 9; ++i) r += f[i * n + k];
+  for (int i = 1; i < 9; ++i) r += fl[i];
   bool cl;
+  p = psi_f64(d, r, cl);
+}
+
+__device__ inline void prep_node(const InstDesc& d, const double* __restrict__ f, int64_t n, int nx, int x, int y,
+                                 AdjScratch& sc) {
+  const unsigned k = (unsigned)((y - 1) * nx + x);  // node counts are below 2^31 (lbm_create checks)
+  double fl[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fl[i] = f[i * n + k];
+  double r, p;
+  node_rho_psi(d, fl, r, p);
   Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
   R.at(x, y) = r;
-  P.at(x, y) = psi_f64(d, r, cl);
+  P.at(x, y) = p;
+}
+
+// density and psi into the scratch field of the four wall-adjacent rows (read by the ghost rows and their adjoint)
+__global__ __launch_bounds__(AB) void ka_prep_rows(const InstDesc* __restrict__ descs, int inst,
+                                                   const double* __restrict__ f, AdjScratch sc) {
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny;
+  const int t = (int)(blockIdx.x * AB + threadIdx.x);
+  if (t >= 4 * nx) return;
+  const int j = t / nx, x = t % nx;
+  const int y = j == 0 ? 1 : (j == 1 ? 2 : (j == 2 ? ny - 3 : ny - 2));
+  if (y < 1 || y > ny - 2) return;
+  prep_node(d, f, (int64_t)nx * (ny - 2), nx, x, y, sc);
 }
 
 // forward ghost rows: density (clamped), psi, and whether the clamp was active (derivative 0)
@@ -98,36 +115,8 @@ __global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ 
   sc.gflag[wall * nx + c] = cl ? 1.0 : 0.0;
 }
 
-__device__ inline void force_at(const InstDesc& d, const Field& P, int nx, int x, int y, double& Fx, double& Fy) {
-  const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
-  const double pm = P.at(x, y - 1), pmL = P.at(xl, y - 1), pmR = P.at(xr, y - 1);
-  const double pc = P.at(x, y), pcL = P.at(xl, y), pcR = P.at(xr, y);
-  const double pn = P.at(x, y + 1), pnL = P.at(xl, y + 1), pnR = P.at(xr, y + 1);
-  const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, A = d.A, Gf = d.G_f;
-  const double spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
-  const double spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
-  const double sux = k1 * (pcR * pcR - pcL * pcL) + k2 * ((pnR * pnR - pnL * pnL) + (pmR * pmR - pmL * pmL));
-  const double suy = k1 * (pn * pn - pm * pm) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
-  Fx = -Gf * (0.5 * A * sux + (1.0 - A) * pc * spx);
-  Fy = -Gf * (0.5 * A * suy + (1.0 - A) * pc * spy);
-}
-
 // 2. streaming and collision transposed at fluid node (x, y): the direct part of lambda_n (lam), F_bar, and the
 //    interaction force F_i (for G_f_bar = F_bar . F_i / G_f).
-// Loads of node (x, y): its populations f and the streamed-back adjoint lambda*_i = lambda_i(x + e_i) (or
-// lambda_{opp(i)}(x) where x + e_i is a ghost row).
-__device__ inline void adj_loads(const double* __restrict__ f, const double* __restrict__ lam1, int64_t n, int nx,
-                                 int ny, int x, int y, double (&fl)[9], double (&ls)[9]) {
-  const unsigned k = (unsigned)((y - 1) * nx + x);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    fl[i] = f[i * n + k];
-    const int yd = y + kEY[i];
-    ls[i] = (yd < 1 || yd > ny - 2) ? lam1[kOPP[i] * n + k]
-                                    : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))];
-  }
-}
-
 __device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fix,
                                    double Fiy, double (&lam)[9], double& Fbx, double& Fby) {
   const double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
@@ -247,17 +236,17 @@ __global__ __launch_bounds__(AB) void ka_ghost_adj(const InstDesc* __restrict__ 
   if (threadIdx.x == 0) sc.part[kAdjBlocks + blockIdx.x] = tot;
 }
 
-// 3 + 5 fused: one wavefront walks a strip of rows [y0, ylast] over at most 62 columns. Row by row it transposes
+// 3 + 5 fused: one wavefront walks a strip of rows [y0, ylast] over at most 60 columns. Row by row it transposes
 // the streaming and collision one row ahead (stage C, also on one halo column at each side and on the rows y0 - 1
-// and ylast + 1), keeps that row's F_bar in a ring of three rows in LDS, and transposes the force and psi for the
+// and ylast + 1; a second halo column at each side only supplies psi), keeps that row's F_bar in a ring of three rows in LDS, and transposes the force and psi for the
 // row behind (stage S): psi_bar from its own force and the eight neighbours' forces, rho_bar = psi_bar dpsi/drho,
-// and lambda_n = direct part + rho_bar, written once. psi stays in a window of four rows in registers (neighbour
-// columns by lane shuffles; the two edge lanes also hold the next column out), and every global load of a row
-// iteration is for a later row (populations and lambda_{n+1} of the next stage C row, psi two rows ahead, rho of
-// the next stage S row), so it is in flight while the current rows are computed. F_bar of the boundary rows 1 and
-// ny-2 also goes to the scratch for the ghost rows' adjoint, whose boundary-row terms ka_wall_fix adds afterwards.
-// Partials of G_f_bar (stage C) and G_psi_bar (stage S) per block, over the block's own columns and rows only.
-constexpr int FL = 64;         // lanes per block (one wavefront): at most 62 own columns, one halo column each side
+// and lambda_n = direct part + rho_bar, written once. Density and psi are computed here from the populations,
+// which are loaded two rows ahead of stage C and kept until it uses them; psi and rho live in a window of rows in
+// registers (neighbour columns by lane shuffles; the ghost rows' psi from the scratch field). Every global load of a row iteration is for a later row, in flight while the current
+// rows are computed. F_bar of the boundary rows 1 and ny-2 also goes to the scratch for the ghost rows' adjoint,
+// whose boundary-row terms ka_wall_fix adds afterwards. Partials of G_f_bar (stage C) and G_psi_bar (stage S) per
+// block, over the block's own columns and rows only.
+constexpr int FL = 64;         // lanes per block (one wavefront): at most 60 own columns, two halo columns each side
 
 // Interaction force (Eq. 9) from the 3 x 3 psi values around the node: rows below (m), own (c), above (n).
 __device__ inline void force_vals(const InstDesc& d, double pmL, double pm, double pmR, double pcL, double pcR,
@@ -272,15 +261,15 @@ __device__ inline void force_vals(const InstDesc& d, double pmL, double pm, doub
 }
 
 __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
-                                               const double* __restrict__ f, const double* __restrict__ lam1,
-                                               double* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
-                                               int ntasks) {
+                                                  const double* __restrict__ f, const double* __restrict__ lam1,
+                                                  double* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
+                                                  int ntasks) {
   __shared__ double ring[3][2][FL];
   __shared__ double ldir[9][FL];  // direct part of lambda_n of the stage C row, read back by the next stage S
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int64_t n = (int64_t)nx * (ny - 2);
-  Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
+  Field P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
   const int l = (int)threadIdx.x;
   const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, Gf = d.G_f, A = d.A;
   double gf_part = 0.0, gpsi = 0.0;
@@ -288,48 +277,94 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
     const int cb = t % ncb, sb = t / ncb;
     const int x0 = cb * bw, w = min(bw, nx - x0);
     const int y0 = 1 + sb * H, ylast = min(ny - 2, y0 + H - 1);
-    const bool act = l <= w + 1;          // lanes 0 .. w+1: columns x0-1 .. x0+w
-    const bool own = l >= 1 && l <= w;    // lanes 1 .. w: the block's own columns
-    const bool ledge = l == 0, redge = l == w + 1;
-    const int x = act ? wrapx(x0 - 1 + l, nx) : 0;
-    const int xo = ledge ? wrapx(x - 1, nx) : wrapx(x + 1, nx);  // next column out (edge lanes only)
+    // lanes 0 .. w+3: columns x0-2 .. x0+w+1 (one period at most: nx >= 2); stage C is valid on lanes 1 .. w+2
+    // (lanes 0 and w+3 only supply psi), stage S runs on the block's own columns, lanes 2 .. w+1
+    const bool act = l <= w + 3;
+    const bool own = l >= 2 && l <= w + 1;
+    const int x = act ? wrapx(x0 - 2 + l, nx) : 0;
     const int yc0 = max(1, y0 - 1), yc1 = min(ny - 2, ylast + 1);
-    // psi window: rows yc-2 (a), yc-1 (b), yc (c), yc+1 (e) at the stage C row yc; o* = the edge lanes' outer column
-    double pa = 0.0, pb = 0.0, pc = 0.0, pe = 0.0, oa = 0.0, ob = 0.0, oc = 0.0, oe = 0.0;
-    auto psi_row = [&](int y, double& v, double& o) {
-      v = act ? P.at(x, y) : 0.0;
-      o = (ledge || redge) ? P.at(xo, y) : 0.0;
-    };
-    psi_row(yc0 - 1, pb, ob);
-    psi_row(yc0, pc, oc);
-    psi_row(yc0 + 1, pe, oe);
-    double lcur[9], flc[9], lsc[9], fln[9], lsn[9];
+    auto fluid = [&](int y) { return y >= 1 && y <= ny - 2; };
+    auto load_f = [&](int y, double (&fl)[9]) {
+      const unsigned k = (unsigned)((y - 1) * nx + x);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lcur[i] = fln[i] = lsn[i] = flc[i] = lsc[i] = 0.0;
-    if (act) adj_loads(f, lam1, n, nx, ny, x, yc0, flc, lsc);
-    double rho_s = act ? R.at(x, yc0) : 0.0;   // rho of the next stage S row (yc0 - 1 is never one)
-    // left / right neighbours of a per-lane value (the edge lanes take the outer column)
-    auto lr = [&](double v, double o, double& L, double& Rr) {
-      const double sl = __shfl(v, l > 0 ? l - 1 : 0, FL), sr = __shfl(v, l < FL - 1 ? l + 1 : FL - 1, FL);
-      L = ledge ? o : sl;
-      Rr = redge ? o : sr;
+      for (int i = 0; i < 9; ++i) fl[i] = act ? f[i * n + k] : 0.0;
+    };
+    auto load_lam = [&](int y, double (&ls)[9]) {
+      const unsigned k = (unsigned)((y - 1) * nx + x);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int yd = y + kEY[i];
+        ls[i] = !act ? 0.0
+                     : ((yd < 1 || yd > ny - 2) ? lam1[kOPP[i] * n + k]
+                                                : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))]);
+      }
+    };
+    // window at the stage C row yc: psi of rows yc-2 (a), yc-1 (b), yc (c), yc+1 (e), rho of rows yc-1 (rb),
+    // yc (rc), yc+1 (re); populations of rows yc (fA), yc+1 (fB); pg the ghost row's psi when row yc+1 is one
+    double pa = 0.0, pb = 0.0, pc = 0.0, pe = 0.0, rb = 0.0, rc = 0.0, re = 0.0, pg = 0.0;
+    double fA[9], fB[9], fN[9], lsA[9], lsN[9], lcur[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fB[i] = fN[i] = lsN[i] = lcur[i] = 0.0;
+    if (fluid(yc0 - 1)) {
+      double ft[9];
+      load_f(yc0 - 1, ft);
+      node_rho_psi(d, ft, rb, pb);
+    } else {
+      pb = act ? P.at(x, yc0 - 1) : 0.0;  // ghost row
+    }
+    load_f(yc0, fA);
+    node_rho_psi(d, fA, rc, pc);
+    if (fluid(yc0 + 1)) load_f(yc0 + 1, fB);
+    else pg = act ? P.at(x, yc0 + 1) : 0.0;
+    load_lam(yc0, lsA);
+    // left / right neighbours of a per-lane value (meaningful on lanes 1 .. w+2)
+    auto lr = [&](double v, double& L, double& Rr) {
+      L = __shfl(v, l > 0 ? l - 1 : 0, FL);
+      Rr = __shfl(v, l < FL - 1 ? l + 1 : FL - 1, FL);
+    };
+    auto stage_s = [&](int ys, double aL, double aR, double bL, double bR, double cL, double cR) {
+      // psi rows ys-1 (a), ys (b), ys+1 (c); rho of row ys in rb
+      const double pv[3][3] = {{aL, pa, aR}, {bL, pb, bR}, {cL, pc, cR}};  // [row ys-1..ys+1][x-1..x+1]
+      const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
+      const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
+      double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
+#pragma unroll
+      for (int q = 1; q < 9; ++q) {
+        const int yn = ys - kEY[q];
+        if (yn < 1 || yn > ny - 2) continue;
+        const int ln = l - kEX[q], slot = yn % 3;
+        const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+        const double fe = ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q];
+        acc += -Gf * wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
+      }
+      if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
+      const double rbar = acc * dpsi_drho(d, rb, pb);
+      const unsigned k = (unsigned)((ys - 1) * nx + x);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rbar;
     };
     for (int yc = yc0; yc <= yc1; ++yc) {
-      // loads for later rows first
-      double pnext = 0.0, onext = 0.0, rho_next = 0.0;
-      if (act && yc < yc1) adj_loads(f, lam1, n, nx, ny, x, yc + 1, fln, lsn);
-      if (yc + 2 <= ny - 1) psi_row(yc + 2, pnext, onext);
-      if (act) rho_next = R.at(x, yc);
-      // stage C at row yc
+      // psi and rho of row yc+1 from its populations (loaded one iteration ago), or the ghost row's psi
+      if (fluid(yc + 1)) node_rho_psi(d, fB, re, pe);
+      else pe = pg;
+      // loads for later rows: populations (or the ghost row's psi) of row yc+2, lambda of row yc+1
+      const int r2 = yc + 2;
+      double pgnext = 0.0;
+      if (r2 <= yc1 + 1) {
+        if (fluid(r2)) load_f(r2, fN);
+        else pgnext = act ? P.at(x, r2) : 0.0;
+      }
+      if (yc < yc1) load_lam(yc + 1, lsN);
+      // stage C at row yc: psi rows yc-1 (b), yc (c), yc+1 (e)
       double bL, bR, cL, cR, eL, eR;
-      lr(pb, ob, bL, bR);
-      lr(pc, oc, cL, cR);
-      lr(pe, oe, eL, eR);
+      lr(pb, bL, bR);
+      lr(pc, cL, cR);
+      lr(pe, eL, eR);
       double Fbx = 0.0, Fby = 0.0;
       if (act) {
         double Fix, Fiy;
         force_vals(d, bL, pb, bR, cL, cR, pc, eL, pe, eR, Fix, Fiy);
-        collide_adj(d, flc, lsc, Fix, Fiy, lcur, Fbx, Fby);
+        collide_adj(d, fA, lsA, Fix, Fiy, lcur, Fbx, Fby);
         if (own) {
           if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) / Gf;  // halo rows belong elsewhere
           if (yc == 1 || yc == ny - 2) {
@@ -342,70 +377,32 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
       ring[yc % 3][0][l] = Fbx;
       ring[yc % 3][1][l] = Fby;
       __syncthreads();
-      // stage S at row ys = yc - 1 from psi rows yc-2 (m), yc-1 (c), yc (n)
-      const int ys = yc - 1;
-      if (ys >= y0 && ys <= ylast) {
+      // stage S at row yc-1: psi rows yc-2 (a), yc-1 (b), yc (c)
+      if (yc - 1 >= y0 && yc - 1 <= ylast) {
         double aL, aR;
-        lr(pa, oa, aL, aR);
-        if (own) {
-          const double pv[3][3] = {{aL, pa, aR}, {bL, pb, bR}, {cL, pc, cR}};  // [row ys-1..ys+1][x-1..x+1]
-          const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
-          const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
-          double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
-#pragma unroll
-          for (int q = 1; q < 9; ++q) {
-            const int yn = ys - kEY[q];
-            if (yn < 1 || yn > ny - 2) continue;
-            const int ln = l - kEX[q], slot = yn % 3;
-            const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-            const double fe = ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q];
-            acc += -Gf * wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
-          }
-          if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
-          const double rb = acc * dpsi_drho(d, rho_s, pb);
-          const unsigned k = (unsigned)((ys - 1) * nx + x);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rb;
-        }
+        lr(pa, aL, aR);
+        if (own) stage_s(yc - 1, aL, aR, bL, bR, cL, cR);
       }
-      // slide: rows move down the window, the loads above become the current ones
-      pa = pb; pb = pc; pc = pe; pe = pnext;
-      oa = ob; ob = oc; oc = oe; oe = onext;
-      rho_s = rho_next;
+      // slide the window one row on
+      pa = pb; pb = pc; pc = pe;
+      rb = rc; rc = re;
+      pg = pgnext;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         ldir[i][l] = lcur[i];  // same lane reads it back at the next stage S
-        flc[i] = fln[i];
-        lsc[i] = lsn[i];
+        fA[i] = fB[i];
+        fB[i] = fN[i];
+        lsA[i] = lsN[i];
       }
     }
-    // the top wall's boundary row: no stage C row above it (row ny-1 is the ghost row, F_bar absent there)
+    // the top wall's boundary row: no stage C row above it (row ny-1 is the ghost row, F_bar absent there);
+    // after the slide the window holds psi rows ny-3 (a), ny-2 (b), ny-1 (c) and rho of row ny-2 in rb
     if (ylast == ny - 2) {
-      const int ys = ylast;  // window after the slide: pa = row ys-1, pb = row ys, pc = row ys+1 (ghost)
       double aL, aR, bL, bR, cL, cR;
-      lr(pa, oa, aL, aR);
-      lr(pb, ob, bL, bR);
-      lr(pc, oc, cL, cR);
-      if (own) {
-        const double pv[3][3] = {{aL, pa, aR}, {bL, pb, bR}, {cL, pc, cR}};
-        const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
-        const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
-        double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
-#pragma unroll
-        for (int q = 1; q < 9; ++q) {
-          const int yn = ys - kEY[q];
-          if (yn < 1 || yn > ny - 2) continue;
-          const int ln = l - kEX[q], slot = yn % 3;
-          const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-          const double fe = ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q];
-          acc += -Gf * wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
-        }
-        if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
-        const double rb = acc * dpsi_drho(d, rho_s, pb);
-        const unsigned k = (unsigned)((ys - 1) * nx + x);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rb;
-      }
+      lr(pa, aL, aR);
+      lr(pb, bL, bR);
+      lr(pc, cL, cR);
+      if (own) stage_s(ylast, aL, aR, bL, bR, cL, cR);
     }
     __syncthreads();  // the ring is reused by the next task
   }
@@ -471,11 +468,9 @@ int adjoint_partials_needed() { return 3 * kAdjBlocks; }
 hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc,
                           const double* f_n, const double* lam_np1, double* lam_n, double* theta_bar, double* G_bar,
                           hipStream_t s) {
-  const int64_t n = (int64_t)h.nx * (h.ny - 2);
-  const unsigned gprep = (unsigned)((n + AB - 1) / AB);
   const unsigned gghost = (unsigned)((2 * h.nx + AB - 1) / AB);
   if (gghost > (unsigned)kAdjBlocks) return hipErrorInvalidValue;
-  // fused pass: column blocks of at most FL - 2 columns (balanced), and row strips sized so that the tasks fit
+  // fused pass: column blocks of at most FL - 4 columns (balanced), and row strips sized so that the tasks fit
   // in one round of resident wavefronts (eight per compute unit at this kernel's register use), at least 4 rows
   static int cus = 0;
   if (cus == 0) {
@@ -483,14 +478,14 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
     cus = (hipGetDevice(&dev) == hipSuccess &&
            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ? v : 256;
   }
-  const int ncb = (h.nx + FL - 3) / (FL - 2);
+  const int ncb = (h.nx + FL - 5) / (FL - 4);
   const int bw = (h.nx + ncb - 1) / ncb;
   const int nyf = h.ny - 2;
   const int strips = std::max(1, std::min(nyf, 8 * cus / ncb));
   const int H = std::max(4, (nyf + strips - 1) / strips);
   const int ntasks = ncb * ((nyf + H - 1) / H);
   const unsigned gfused = (unsigned)std::min(ntasks, kAdjBlocks);
-  hipLaunchKernelGGL(ka_prep, dim3(gprep), dim3(AB), 0, s, d_desc, inst, f_n, sc);
+  hipLaunchKernelGGL(ka_prep_rows, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n, sc);
   hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
   hipLaunchKernelGGL(ka_fused, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb, H,
                      ntasks);
