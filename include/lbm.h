@@ -60,7 +60,7 @@ typedef enum {
   LBM_WALLS_MARTYS_CHEN = 2  /* the comparison method of Sec. 3: rows 0 and ny-1 are solid walls that attract the
                           fluid through the force of Eq. 14 (strength G_w per wall) and take no part in the
                           fluid-fluid force (psi = 0 there; they read back as 0); halfway bounce-back as for
-                          LBM_WALLS_Y, no geometric wetting (contact angles unused). Forward only. */
+                          LBM_WALLS_Y, no geometric wetting (contact angles unused; theta_bar stays 0). */
 } lbm_boundary;
 
 typedef enum {
@@ -103,7 +103,7 @@ typedef struct {
   double mrt_rates[3];    /* s_e, s_eps, s_q of Eq. 2 (tau_e^-1, tau_xi^-1, tau_q^-1), each 0 (= 1/tau) or in
                              (0, 2). Any non-zero rate, or kappa != 0, selects the MRT collision of Eq. 15 (stress
                              relaxed at 1/tau; the conserved moments' rates do not enter); all 0 with kappa = 0 is
-                             BGK, the same scheme up to rounding. Excludes enable_adjoint. [0, 0, 0] */
+                             BGK, the same scheme up to rounding. [0, 0, 0] */
   double kappa;           /* surface-tension parameter of Eq. 16-17: the source C with Q = kappa (G/2)[...] scales
                              the surface tension by 1 - kappa and leaves flat-interface densities unchanged. [0] */
   double G_w[2];          /* LBM_WALLS_MARTYS_CHEN: G_w of Eq. 14 for the bottom and top wall (more negative
@@ -200,9 +200,11 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
  * Given the FP64 populations f_n of step n (d_state_n, [9][ny-2][nx], unshifted) and the adjoint
  * lambda_{n+1} = dL/df_{n+1} (same layout), writes lambda_n = (d f_{n+1} / d f_n)^T lambda_{n+1} to d_lambda_n
  * and ACCUMULATES d_theta_bar[2][nx] += (d f_{n+1}/d theta)^T lambda_{n+1} (bottom row then top row) and
- * d_G_bar[2] += {dL/dG_f, dL/dG_psi}, G_f being the force prefactor of Eq. 9 and G_psi the G inside Eq. 10
- * (equal in the forward model, so their sum is the total derivative, zero for this model). Needs
- * enable_adjoint = 1. The adjoint is evaluated in FP64 at the given state for every precision: for an FP32
+ * d_G_bar[2] += {dL/dG_f, dL/dG_psi}, G_f being the prefactor of the force of Eq. 9 and of Q in Eq. 17 and G_psi
+ * the G inside Eq. 10 (equal in the forward model, so their sum is the total derivative: zero with geometric walls,
+ * where every term depends on G_f / G_psi only; the fluid-solid force of Eq. 14 scales with psi alone). Covers the
+ * BGK and MRT collisions with the source of Eq. 16-17, both EOS, geometric and Martys-Chen walls (not
+ * LBM_PERIODIC_Y). Needs enable_adjoint = 1. The adjoint is evaluated in FP64 at the given state for every precision: for an FP32
  * instance it differentiates the FP32 trajectory (pass its populations from lbm_get_populations). Runs on the
  * context's stream; sub-gradient 0 at exact kinks (|T| of Eq. 19, the square root at 0, the clamps). Does not
  * change the context's state. */

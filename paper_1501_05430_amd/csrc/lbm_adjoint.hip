@@ -106,6 +106,12 @@ __global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ 
   const int wall = t / nx, c = t % nx;
   Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
   const int g = wall == 0 ? 0 : ny - 1, r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
+  if (d.wall_mc) {  // solid wall rows (Eq. 14): psi = 0 there, no dependence on the state
+    R.at(c, g) = 0.0;
+    P.at(c, g) = 0.0;
+    sc.gflag[wall * nx + c] = 1.0;
+    return;
+  }
   bool cl;
   const double r0 = ghost_density(R.at(wrapx(c - 1, nx), r1), R.at(wrapx(c + 1, nx), r1), R.at(c, r1), R.at(c, r2),
                                   d.cos_th[wall * nx + c], d.cot_th[wall * nx + c], d.wet_iters, d.rho_cap_hi, cl);
@@ -115,11 +121,10 @@ __global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ 
   sc.gflag[wall * nx + c] = cl ? 1.0 : 0.0;
 }
 
-// 2. streaming and collision transposed at fluid node (x, y): the direct part of lambda_n (lam), F_bar, and the
-//    interaction force F_i (for G_f_bar = F_bar . F_i / G_f).
-__device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fix,
-                                   double Fiy, double (&lam)[9], double& Fbx, double& Fby) {
-  const double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
+// 2. streaming and collision transposed at a fluid node, BGK: given lambda* (ls) and the node's total force F, the
+//    direct part of lambda_n (lam) and F_bar.
+__device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fx,
+                                   double Fy, double (&lam)[9], double& Fbx, double& Fby) {
   // forward collision quantities
   const double rho = sum9(fl);
   const double jx = mom_x(fl), jy = mom_y(fl);
@@ -153,9 +158,72 @@ __device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], con
   for (int i = 0; i < 9; ++i) lam[i] += rhob + jbx * kEX[i] + jby * kEY[i];
 }
 
-// psi_bar at node y from the force of node x = y - e_a (x a fluid node): -G_f w_a (F_bar(x).e_a)(A psi(y) + (1-A) psi(x))
-__device__ inline double psi_bar_from(const InstDesc& d, const Field& P, const Field& FX, const Field& FY, int nx,
-                                      int ny, int x0, int y0) {
+// D2Q9 moment basis in the order of Eq. 4 (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) and its row norms.
+constexpr int kMom[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},       {-4, -1, -1, -1, -1, 2, 2, 2, 2}, {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},    {0, -2, 0, 2, 0, 1, -1, -1, 1},   {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},    {0, 1, -1, 1, -1, 0, 0, 0, 0},    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+constexpr double kMomNorm[9] = {9.0, 36.0, 36.0, 6.0, 12.0, 6.0, 12.0, 4.0, 4.0};
+
+// 2'. the MRT collision of Eq. 15 transposed. Forward: f* = f + M^-1 dm with dm_k = -s_k (m_k - m_eq,k)
+//     + (1 - s_k/2) S_k + C_k on the non-conserved moments and dm = F on j. Reverse: dm_bar = D^-1 M lambda*, then
+//     the relaxation (through m = M f), the equilibria and forcing moments (through rho and v = (j + F/2)/rho) and
+//     the source (Q_bar, the adjoint of Q of Eq. 17, xx / yy / xy).
+__device__ inline void collide_mrt_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fx,
+                                       double Fy, double (&lam)[9], double& Fbx, double& Fby, double (&qb)[3]) {
+  const double rho = sum9(fl), jx = mom_x(fl), jy = mom_y(fl);
+  const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
+  const double v2 = vx * vx + vy * vy;
+  const double sn = d.inv_tau;
+  const double sr[9] = {0.0, d.s_e, d.s_eps, 0.0, d.s_q, 0.0, d.s_q, sn, sn};
+  const double meq[9] = {rho, rho * (-2.0 + 3.0 * v2), rho * (1.0 - 3.0 * v2), rho * vx, -rho * vx, rho * vy,
+                         -rho * vy, rho * (vx * vx - vy * vy), rho * vx * vy};
+  double dmb[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a += kMom[k][i] * ls[i];
+    dmb[k] = a / kMomNorm[k];
+  }
+  double a[9], b[9], mb[9];
+  double rhob = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const bool nc = k == 1 || k == 2 || k == 4 || k == 6 || k == 7 || k == 8;
+    mb[k] = nc ? -sr[k] * dmb[k] : 0.0;               // through m_k = (M f)_k
+    a[k] = nc ? sr[k] * dmb[k] : 0.0;                 // adjoint of m_eq,k
+    b[k] = nc ? (1.0 - 0.5 * sr[k]) * dmb[k] : 0.0;   // adjoint of S_k
+    rhob += a[k] * meq[k] / rho;
+  }
+  double vbx = 6.0 * rho * vx * (a[1] - a[2]) - rho * a[4] + 2.0 * rho * vx * a[7] + rho * vy * a[8];
+  double vby = 6.0 * rho * vy * (a[1] - a[2]) - rho * a[6] - 2.0 * rho * vy * a[7] + rho * vx * a[8];
+  vbx += 6.0 * Fx * (b[1] - b[2]) + 2.0 * Fx * b[7] + Fy * b[8];
+  vby += 6.0 * Fy * (b[1] - b[2]) - 2.0 * Fy * b[7] + Fx * b[8];
+  Fbx = dmb[3] + 6.0 * vx * (b[1] - b[2]) - b[4] + 2.0 * vx * b[7] + vy * b[8];
+  Fby = dmb[5] + 6.0 * vy * (b[1] - b[2]) - b[6] - 2.0 * vy * b[7] + vx * b[8];
+  qb[0] = 1.5 * d.s_e * dmb[1] - sn * dmb[7];
+  qb[1] = 1.5 * d.s_e * dmb[1] + sn * dmb[7];
+  qb[2] = -sn * dmb[8];
+  // v = (j + F/2) / rho
+  const double jbx = vbx / rho, jby = vby / rho;
+  Fbx += 0.5 * vbx / rho;
+  Fby += 0.5 * vby / rho;
+  rhob -= (vbx * vx + vby * vy) / rho;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double m = 0.0;
+#pragma unroll
+    for (int k = 1; k < 9; ++k) m += kMom[k][i] * mb[k];
+    lam[i] = ls[i] + m + rhob + jbx * kEX[i] + jby * kEY[i];
+  }
+}
+
+// psi_bar at node y from the force of node x = y - e_a (x a fluid node): -G_f w_a (F_bar(x).e_a)(A psi(y) + (1-A) psi(x)),
+// plus, with the surface-tension source, kq w_a (Q_bar(x) : e_a e_a)(A psi(y) + (1-A) psi(x)) from Q of Eq. 17
+// (qwall: Q_bar of the boundary rows, or NULL).
+__device__ inline double psi_bar_from(const InstDesc& d, const Field& P, const Field& FX, const Field& FY,
+                                      const double* qwall, int nx, int ny, int x0, int y0) {
   double acc = 0.0;
   const double py = P.at(x0, y0);
 #pragma unroll
@@ -163,8 +231,12 @@ __device__ inline double psi_bar_from(const InstDesc& d, const Field& P, const F
     const int xs = wrapx(x0 - kEX[a], nx), ys = y0 - kEY[a];
     if (ys < 1 || ys > ny - 2) continue;
     const double wa = a < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-    const double fe = FX.at(xs, ys) * kEX[a] + FY.at(xs, ys) * kEY[a];
-    acc += -d.G_f * wa * fe * (d.A * py + (1.0 - d.A) * P.at(xs, ys));
+    double fe = -d.G_f * (FX.at(xs, ys) * kEX[a] + FY.at(xs, ys) * kEY[a]);
+    if (qwall) {  // the source's Q at the boundary-row node xs (Eq. 17) also reads psi here
+      const double* q = qwall + (ys == 1 ? 0 : 3) * nx;
+      fe += d.kq * (q[xs] * kEX[a] * kEX[a] + q[nx + xs] * kEY[a] * kEY[a] + q[2 * nx + xs] * kEX[a] * kEY[a]);
+    }
+    acc += wa * fe * (d.A * py + (1.0 - d.A) * P.at(xs, ys));
   }
   return acc;
 }
@@ -182,7 +254,7 @@ __global__ __launch_bounds__(AB) void ka_ghost_adj(const InstDesc* __restrict__ 
   if (t < 2 * nx) {
     const int wall = t / nx, c = t % nx;
     const int g = wall == 0 ? 0 : ny - 1, r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
-    const double pb = psi_bar_from(d, P, FX, FY, nx, ny, c, g);
+    const double pb = psi_bar_from(d, P, FX, FY, (d.mrt && d.kq != 0.0) ? sc.qwall : nullptr, nx, ny, c, g);
     const double psi0 = P.at(c, g), rho0 = R.at(c, g);
     if (psi0 > 0.0) gpsi += pb * (-psi0 * 0.5 * d.two_over_Gpsi * 0.5);  // d psi / d G_psi = -psi / (2 G_psi)
     double rb0 = sc.gflag[wall * nx + c] != 0.0 ? 0.0 : pb * dpsi_drho(d, rho0, psi0);
@@ -260,11 +332,15 @@ __device__ inline void force_vals(const InstDesc& d, double pmL, double pm, doub
   Fy = -Gf * (0.5 * A * suy + (1.0 - A) * pc * spy);
 }
 
-__global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
+// EXT: the MRT collision with the source of Eq. 16-17 (Q_bar joins F_bar in the ring) and the fluid-solid force of
+// Eq. 14 on the boundary rows; without it only the BGK collision with geometric walls is compiled.
+template <bool EXT>
+__global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
                                                   const double* __restrict__ f, const double* __restrict__ lam1,
                                                   double* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
                                                   int ntasks) {
-  __shared__ double ring[3][2][FL];
+  constexpr int NR = EXT ? 5 : 2;  // per node in the ring: F_bar (x, y), then Q_bar (xx, yy, xy)
+  __shared__ double ring[3][NR][FL];
   __shared__ double ldir[9][FL];  // direct part of lambda_n of the stage C row, read back by the next stage S
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
@@ -272,6 +348,8 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
   Field P{sc.psi, d.pitch}, FX{sc.Fbar, d.pitch}, FY{sc.Fbar + (int64_t)ny * d.pitch, d.pitch};
   const int l = (int)threadIdx.x;
   const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, Gf = d.G_f, A = d.A;
+  const bool mrt = EXT && d.mrt != 0, mcw = EXT && d.wall_mc != 0;
+  const double kq = mrt ? d.kq : 0.0, gwb = d.gw_half[0], gwt = d.gw_half[1];
   double gf_part = 0.0, gpsi = 0.0;
   for (int t = (int)blockIdx.x; t < ntasks; t += (int)gridDim.x) {
     const int cb = t % ncb, sb = t / ncb;
@@ -328,14 +406,34 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
       const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
       const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
       double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
+      if constexpr (EXT) {
+        // fluid-solid force of Eq. 14 on the boundary rows: F_s,y = +-(G_w / 2) psi
+        if (mcw && ys == 1) acc += gwb * ring[ys % 3][1][l];
+        if (mcw && ys == ny - 2) acc -= gwt * ring[ys % 3][1][l];
+        if (kq != 0.0) {
+          // own Q (Eq. 17): d Q / d psi(x) = kq [(1 - A) a - psi W], a = sum_a w_a (psi_a - psi) e_a e_a, W = I
+          const double dg = ((cR + cL) + (aR + aL)) - 4.0 * pb;
+          const double axx = k1 * ((bR + bL) - 2.0 * pb) + k2 * dg;
+          const double ayy = k1 * ((pc + pa) - 2.0 * pb) + k2 * dg;
+          const double axy = k2 * ((cR - cL) - (aR - aL));
+          const double* qo = &ring[ys % 3][2][0];
+          const double qxx = qo[l], qyy = qo[FL + l], qxy = qo[2 * FL + l];
+          acc += kq * ((1.0 - A) * (qxx * axx + qyy * ayy + qxy * axy) - pb * (qxx + qyy));
+        }
+      }
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
         const int yn = ys - kEY[q];
         if (yn < 1 || yn > ny - 2) continue;
         const int ln = l - kEX[q], slot = yn % 3;
         const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-        const double fe = ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q];
-        acc += -Gf * wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
+        double fe = -Gf * (ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q]);
+        if constexpr (EXT) {
+          if (kq != 0.0)  // the neighbour's Q reads psi here (Eq. 17)
+            fe += kq * (ring[slot][2][ln] * (kEX[q] * kEX[q]) + ring[slot][3][ln] * (kEY[q] * kEY[q]) +
+                        ring[slot][4][ln] * (kEX[q] * kEY[q]));
+        }
+        acc += wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
       }
       if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
       const double rbar = acc * dpsi_drho(d, rb, pb);
@@ -360,22 +458,46 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
       lr(pb, bL, bR);
       lr(pc, cL, cR);
       lr(pe, eL, eR);
-      double Fbx = 0.0, Fby = 0.0;
+      double Fbx = 0.0, Fby = 0.0, qb[3] = {0.0, 0.0, 0.0};
       if (act) {
         double Fix, Fiy;
         force_vals(d, bL, pb, bR, cL, cR, pc, eL, pe, eR, Fix, Fiy);
-        collide_adj(d, fA, lsA, Fix, Fiy, lcur, Fbx, Fby);
+        double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
+        if (mcw && yc == 1) Fy = Fy + gwb * pc;        // Eq. 14 next to the bottom wall
+        if (mcw && yc == ny - 2) Fy = Fy - gwt * pc;   // and next to the top wall
+        double gq = 0.0;
+        if (mrt) {
+          collide_mrt_adj(d, fA, lsA, Fx, Fy, lcur, Fbx, Fby, qb);
+          if (kq != 0.0) {  // Q is proportional to G_f: G_f_bar += Q_bar : Q / G_f
+            double qxx, qyy, qxy;
+            qtensor<double>(pc, cL, cR, pe, eL, eR, pb, bL, bR, A, kq, qxx, qyy, qxy);
+            gq = (qb[0] * qxx + qb[1] * qyy + qb[2] * qxy) / Gf;
+          }
+        } else {
+          collide_adj(d, fA, lsA, Fx, Fy, lcur, Fbx, Fby);
+        }
         if (own) {
-          if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) / Gf;  // halo rows belong elsewhere
+          if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) / Gf + gq;  // halo rows belong elsewhere
           if (yc == 1 || yc == ny - 2) {
             FX.at(x, yc) = Fbx;
             FY.at(x, yc) = Fby;
+            if (kq != 0.0) {
+              double* q = sc.qwall + (yc == 1 ? 0 : 3) * nx;
+              q[x] = qb[0];
+              q[nx + x] = qb[1];
+              q[2 * nx + x] = qb[2];
+            }
           }
         }
       }
       __syncthreads();  // the slot written next was read by stage S two rows back
       ring[yc % 3][0][l] = Fbx;
       ring[yc % 3][1][l] = Fby;
+      if constexpr (EXT) {
+        ring[yc % 3][2][l] = qb[0];
+        ring[yc % 3][3][l] = qb[1];
+        ring[yc % 3][4][l] = qb[2];
+      }
       __syncthreads();
       // stage S at row yc-1: psi rows yc-2 (a), yc-1 (b), yc (c)
       if (yc - 1 >= y0 && yc - 1 <= ylast) {
@@ -487,8 +609,12 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
   const unsigned gfused = (unsigned)std::min(ntasks, kAdjBlocks);
   hipLaunchKernelGGL(ka_prep_rows, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n, sc);
   hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
-  hipLaunchKernelGGL(ka_fused, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb, H,
-                     ntasks);
+  if (h.mrt || h.wall_mc)
+    hipLaunchKernelGGL(ka_fused<true>, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
+                       H, ntasks);
+  else
+    hipLaunchKernelGGL(ka_fused<false>, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
+                       H, ntasks);
   hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
   hipLaunchKernelGGL(ka_wall_fix, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, lam_n,
                      sc);

@@ -255,7 +255,7 @@ size_t adj_bytes(const lbm_params& p) {
   const size_t pitch = (size_t)((p.nx + 63) / 64 * 64);
   const size_t field = align256(sizeof(double) * pitch * p.ny);
   return 4 * field + align256(sizeof(double) * 2 * p.nx) + align256(sizeof(double) * 8 * p.nx) +
-         align256(sizeof(double) * adjoint_partials_needed());
+         align256(sizeof(double) * 6 * p.nx) + align256(sizeof(double) * adjoint_partials_needed());
 }
 
 bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
@@ -280,9 +280,8 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.boundary != LBM_WALLS_Y && q.boundary != LBM_PERIODIC_Y && q.boundary != LBM_WALLS_MARTYS_CHEN)
       return bad("unknown boundary");
     if (!std::isfinite(q.G_w[0]) || !std::isfinite(q.G_w[1])) return bad("G_w not finite");
-    if (q.boundary == LBM_WALLS_MARTYS_CHEN && q.enable_adjoint) return bad("the adjoint supports LBM_WALLS_Y only");
     if (q.eos != LBM_EOS_CARNAHAN_STARLING && q.eos != LBM_EOS_PIECEWISE_LINEAR) return bad("unknown eos");
-    if (q.boundary == LBM_PERIODIC_Y && q.enable_adjoint) return bad("the adjoint supports LBM_WALLS_Y only");
+    if (q.boundary == LBM_PERIODIC_Y && q.enable_adjoint) return bad("the adjoint supports walls only (not LBM_PERIODIC_Y)");
     if ((int64_t)((q.nx + 63) / 64 * 64) * (q.ny - 2) * 9 >= ((int64_t)1 << 31)) return bad("lattice too large for 32-bit offsets");
     if (!(q.tau > 0.5) || !std::isfinite(q.tau)) return bad("tau must be > 0.5");
     if (!(q.G < 0) || !std::isfinite(q.G)) return bad("G must be negative");
@@ -312,7 +311,6 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
       if (!(q.mrt_rates[k] == 0.0 || (q.mrt_rates[k] > 0.0 && q.mrt_rates[k] < 2.0)))
         return bad("mrt_rates must be 0 (= 1/tau) or in (0, 2)");
     if (!std::isfinite(q.kappa)) return bad("kappa not finite");
-    if (uses_mrt(q) && q.enable_adjoint) return bad("the adjoint supports the BGK collision only (mrt_rates = 0, kappa = 0)");
   }
   return true;
 }
@@ -1068,7 +1066,9 @@ int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const do
   sc.Fbar = (double*)(base + 2 * field);
   sc.gflag = (double*)(base + 4 * field);
   sc.wet = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx));
-  sc.part = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx) + align256(sizeof(double) * 8 * nx));
+  sc.qwall = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx) + align256(sizeof(double) * 8 * nx));
+  sc.part = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx) + align256(sizeof(double) * 8 * nx) +
+                      align256(sizeof(double) * 6 * nx));
   if (2 * nx > 1024 * 256) return fail(LBM_E_UNSUPPORTED, "adjoint: nx too large");
   HIP_TRY(launch_adjoint(c->d_desc(), c->hdesc[inst], inst, sc, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar,
                          d_G_bar, c->stream));

@@ -98,6 +98,7 @@ struct AdjScratch {
   double* Fbar;   // [2][ny][pitch]  adjoint of the force at fluid nodes (x then y component)
   double* gflag;  // [2][nx]  1 where the forward ghost density was clamped
   double* wet;    // [2][4][nx]  adjoints of the densities feeding each ghost column
+  double* qwall;  // [2][3][nx]  adjoint of Q (Eq. 17: xx, yy, xy) on the boundary rows 1 and ny-2
   double* part;   // [adjoint_partials_needed()] reduction partials for G_bar
 };
 int adjoint_partials_needed();
