@@ -71,3 +71,59 @@ def test_adjoint_step_dot_product(ora, name):
         if abs(lhs - terms.sum()) > 1e-10 * scale:
             bad.append((k, lhs, float(terms.sum()), (lhs - terms.sum()) / scale))
     assert not bad, bad
+
+
+def test_rollout_gradient_in_the_papers_setting_vs_central_fd():
+    """End to end in the paper's own model (Table 1 EOS at a density ratio of 10, kappa = 0.5 with the relaxation
+    matrix diag(0,1,...,1), A = -0.6): a semicircle R = 20 on a 128 x 64 lattice with wall angles 90 deg +- N(0, 10 deg)
+    per node, 1000 steps, loss ||rho - rho_target|| against the run with 60 deg walls. The checkpointed rollout's
+    gradient with respect to the wall angles matches central finite differences (h = 1e-6) of the GPU forward run
+    at the contact lines, at random columns and on the top wall; dL/dG_f + dL/dG_psi = 0 (geometric walls)."""
+    import torch
+    import paper_1501_05430_amd as P
+    from paper_1501_05430_amd.autograd import Rollout, rollout
+    nx, ny, steps = 128, 64, 1000
+    rng = np.random.default_rng(1501)
+    tb0 = np.radians(90.0 + rng.normal(0.0, 10.0, nx))
+    tt0 = np.radians(90.0 + rng.normal(0.0, 10.0, nx))
+    sim = P.LBM(P.make_params(nx, ny, 1.0, piecewise=PW10, kappa=0.5, enable_adjoint=True))
+    sim.apply_wetting(tb0, tt0)
+    sim.init_droplet(nx / 2, 0.5, 20.0)
+    f0 = sim.populations(device=True)
+    th60 = np.full(nx, np.radians(60.0))
+    sim.apply_wetting(th60, th60)
+    sim.set_populations(f0)
+    sim.step(steps)
+    target = sim.rho(device=True)[1:-1].clone()
+
+    def loss(b, t):
+        sim.apply_wetting(b, t)
+        sim.set_populations(f0)
+        sim.step(steps)
+        return float(torch.linalg.norm(sim.rho(device=True)[1:-1] - target))
+
+    tb = torch.tensor(tb0, dtype=torch.float64, requires_grad=True)
+    tt = torch.tensor(tt0, dtype=torch.float64, requires_grad=True)
+    rho = rollout(tb, tt, -1.0, sim, f0, steps, seg=100)
+    L = torch.linalg.norm(rho - target.to(rho.device))
+    L.backward()
+    gb, gt = tb.grad.numpy(), tt.grad.numpy()
+    assert float(L.detach()) == pytest.approx(loss(tb0, tt0), rel=1e-13)
+    h = 1e-6
+    fd, ad = [], []
+    for wall, cols in ((0, [42, 43, 44, 45, 83, 84, 85, 86, 10, 110]), (1, [5, 64])):
+        for c in cols:
+            vals = []
+            for sgn in (1, -1):
+                b, t = tb0.copy(), tt0.copy()
+                (b if wall == 0 else t)[c] += sgn * h
+                vals.append(loss(b, t))
+            fd.append((vals[0] - vals[1]) / (2 * h))
+            ad.append((gb if wall == 0 else gt)[c])
+    sim.close()
+    fd, ad = np.array(fd), np.array(ad)
+    print("\n  max |adjoint - FD| / max |FD| =", np.abs(ad - fd).max() / np.abs(fd).max())
+    assert np.abs(fd).max() > 0
+    assert np.abs(ad - fd).max() <= 1e-4 * np.abs(fd).max(), np.c_[ad, fd]
+    gf, gpsi = Rollout.last_G_parts
+    assert abs(gf + gpsi) <= 1e-9 * abs(gf)
