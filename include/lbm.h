@@ -56,7 +56,7 @@ typedef enum {
 typedef enum {
   LBM_WALLS_Y = 0,     /* rows 0 and ny-1 are the walls' ghost rows (Sec. 4 wetting, halfway bounce-back) */
   LBM_PERIODIC_Y = 1,  /* no walls: fluid rows 1..ny-2 wrap around (a periodic lattice of ny-2 rows; the ghost
-                          rows are unused and read back as 0). x is periodic in all cases. Forward only. */
+                          rows are unused and read back as 0). x is periodic in all cases. */
   LBM_WALLS_MARTYS_CHEN = 2  /* the comparison method of Sec. 3: rows 0 and ny-1 are solid walls that attract the
                           fluid through the force of Eq. 14 (strength G_w per wall) and take no part in the
                           fluid-fluid force (psi = 0 there; they read back as 0); halfway bounce-back as for
@@ -87,7 +87,7 @@ typedef struct {
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects 1, 2, 4 or 8 wavefronts (64, 128, 256 or 512
                              aligned columns) per block; 0 = library default. Instance 0's value applies to the
                              whole context (lbm_autotune may change it). Results do not depend on it (bitwise). */
-  int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y]; LBM_PERIODIC_Y excludes enable_adjoint */
+  int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y] */
   int32_t eos;            /* lbm_eos [LBM_EOS_CARNAHAN_STARLING] */
   double tau;             /* BGK relaxation time (> 0.5) [1.0] */
   double G;               /* interaction strength, < 0 [-1.0] */
@@ -203,8 +203,8 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
  * d_G_bar[2] += {dL/dG_f, dL/dG_psi}, G_f being the prefactor of the force of Eq. 9 and of Q in Eq. 17 and G_psi
  * the G inside Eq. 10 (equal in the forward model, so their sum is the total derivative: zero with geometric walls,
  * where every term depends on G_f / G_psi only; the fluid-solid force of Eq. 14 scales with psi alone). Covers the
- * BGK and MRT collisions with the source of Eq. 16-17, both EOS, geometric and Martys-Chen walls (not
- * LBM_PERIODIC_Y). Needs enable_adjoint = 1. The adjoint is evaluated in FP64 at the given state for every precision: for an FP32
+ * BGK and MRT collisions with the source of Eq. 16-17, both EOS, geometric and Martys-Chen walls and periodic rows
+ * (theta_bar stays 0 without geometric walls). Needs enable_adjoint = 1. The adjoint is evaluated in FP64 at the given state for every precision: for an FP32
  * instance it differentiates the FP32 trajectory (pass its populations from lbm_get_populations). Runs on the
  * context's stream; sub-gradient 0 at exact kinks (|T| of Eq. 19, the square root at 0, the clamps). Does not
  * change the context's state. */

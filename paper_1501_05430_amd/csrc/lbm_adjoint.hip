@@ -349,6 +349,8 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
   const int l = (int)threadIdx.x;
   const double k1 = 1.0 / 3.0, k2 = 1.0 / 12.0, Gf = d.G_f, A = d.A;
   const bool mrt = EXT && d.mrt != 0, mcw = EXT && d.wall_mc != 0;
+  const bool py = d.periodic_y != 0;  // periodic rows: rows are walked as virtual rows, wrapped to 1 .. ny-2
+  auto wy = [&](int y) { return y < 1 ? y + (ny - 2) : (y > ny - 2 ? y - (ny - 2) : y); };
   const double kq = mrt ? d.kq : 0.0, gwb = d.gw_half[0], gwt = d.gw_half[1];
   double gf_part = 0.0, gpsi = 0.0;
   for (int t = (int)blockIdx.x; t < ntasks; t += (int)gridDim.x) {
@@ -360,21 +362,24 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
     const bool act = l <= w + 3;
     const bool own = l >= 2 && l <= w + 1;
     const int x = act ? wrapx(x0 - 2 + l, nx) : 0;
-    const int yc0 = max(1, y0 - 1), yc1 = min(ny - 2, ylast + 1);
-    auto fluid = [&](int y) { return y >= 1 && y <= ny - 2; };
+    const int yc0 = py ? y0 - 1 : max(1, y0 - 1), yc1 = py ? ylast + 1 : min(ny - 2, ylast + 1);
+    auto fluid = [&](int y) { return py || (y >= 1 && y <= ny - 2); };
     auto load_f = [&](int y, double (&fl)[9]) {
-      const unsigned k = (unsigned)((y - 1) * nx + x);
+      const unsigned k = (unsigned)((wy(y) - 1) * nx + x);
 #pragma unroll
       for (int i = 0; i < 9; ++i) fl[i] = act ? f[i * n + k] : 0.0;
     };
     auto load_lam = [&](int y, double (&ls)[9]) {
-      const unsigned k = (unsigned)((y - 1) * nx + x);
+      const int yw = wy(y);
+      const unsigned k = (unsigned)((yw - 1) * nx + x);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const int yd = y + kEY[i];
+        int yd = yw + kEY[i];
+        const bool wall = !py && (yd < 1 || yd > ny - 2);
+        if (py) yd = wy(yd);
         ls[i] = !act ? 0.0
-                     : ((yd < 1 || yd > ny - 2) ? lam1[kOPP[i] * n + k]
-                                                : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))]);
+                     : (wall ? lam1[kOPP[i] * n + k]
+                             : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))]);
       }
     };
     // window at the stage C row yc: psi of rows yc-2 (a), yc-1 (b), yc (c), yc+1 (e), rho of rows yc-1 (rb),
@@ -424,7 +429,7 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
         const int yn = ys - kEY[q];
-        if (yn < 1 || yn > ny - 2) continue;
+        if (!py && (yn < 1 || yn > ny - 2)) continue;
         const int ln = l - kEX[q], slot = yn % 3;
         const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
         double fe = -Gf * (ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q]);
@@ -437,7 +442,7 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
       }
       if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
       const double rbar = acc * dpsi_drho(d, rb, pb);
-      const unsigned k = (unsigned)((ys - 1) * nx + x);
+      const unsigned k = (unsigned)((wy(ys) - 1) * nx + x);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rbar;
     };
@@ -478,7 +483,7 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
         }
         if (own) {
           if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) / Gf + gq;  // halo rows belong elsewhere
-          if (yc == 1 || yc == ny - 2) {
+          if (!py && (yc == 1 || yc == ny - 2)) {
             FX.at(x, yc) = Fbx;
             FY.at(x, yc) = Fby;
             if (kq != 0.0) {
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
     }
     // the top wall's boundary row: no stage C row above it (row ny-1 is the ghost row, F_bar absent there);
     // after the slide the window holds psi rows ny-3 (a), ny-2 (b), ny-1 (c) and rho of row ny-2 in rb
-    if (ylast == ny - 2) {
+    if (!py && ylast == ny - 2) {
       double aL, aR, bL, bR, cL, cR;
       lr(pa, aL, aR);
       lr(pb, bL, bR);
@@ -607,18 +612,24 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
   const int H = std::max(4, (nyf + strips - 1) / strips);
   const int ntasks = ncb * ((nyf + H - 1) / H);
   const unsigned gfused = (unsigned)std::min(ntasks, kAdjBlocks);
-  hipLaunchKernelGGL(ka_prep_rows, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n, sc);
-  hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
+  const bool walls = h.periodic_y == 0;  // periodic rows have no ghost rows and no wetting
+  if (walls) {
+    hipLaunchKernelGGL(ka_prep_rows, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n,
+                       sc);
+    hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
+  }
   if (h.mrt || h.wall_mc)
     hipLaunchKernelGGL(ka_fused<true>, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
                        H, ntasks);
   else
     hipLaunchKernelGGL(ka_fused<false>, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
                        H, ntasks);
-  hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
-  hipLaunchKernelGGL(ka_wall_fix, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, lam_n,
-                     sc);
-  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(AB), 0, s, sc, (int)gfused, (int)gghost, G_bar);
+  if (walls) {
+    hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
+    hipLaunchKernelGGL(ka_wall_fix, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, lam_n,
+                       sc);
+  }
+  hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(AB), 0, s, sc, (int)gfused, walls ? (int)gghost : 0, G_bar);
   return hipGetLastError();
 }
 

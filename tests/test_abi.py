@@ -62,7 +62,6 @@ def test_workspace_bytes_and_validation():
         dict(nx=20, ny=10, T_over_Tc=0.8, rho0_shift=0.3),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary=3),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary="martys_chen", G_w=(float("inf"), -1.0)),
-        dict(nx=20, ny=10, T_over_Tc=0.8, boundary="periodic", enable_adjoint=True),
         dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, 2.0, 1.0)),
         dict(nx=20, ny=10, T_over_Tc=0.8, mrt=(1.2, -0.5, 1.0)),
         dict(nx=20, ny=10, T_over_Tc=0.8, kappa=float("nan")),

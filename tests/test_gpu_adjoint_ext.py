@@ -127,3 +127,45 @@ def test_rollout_gradient_in_the_papers_setting_vs_central_fd():
     assert np.abs(ad - fd).max() <= 1e-4 * np.abs(fd).max(), np.c_[ad, fd]
     gf, gpsi = Rollout.last_G_parts
     assert abs(gf + gpsi) <= 1e-9 * abs(gf)
+
+
+@pytest.mark.parametrize("nx,ny,T,kw", [
+    (40, 12, 0.75, dict(tau=0.8, body_force=(1e-5, -2e-6))),
+    (33, 5, 0.75, dict(A=0.0)),
+    (40, 12, 1.0, dict(piecewise=PW10, kappa=0.5, tau=0.9, mrt=(1.2, 1.4, 1.1))),
+], ids=["bgk", "shan_chen_5rows", "mrt_kappa_pw10"])
+def test_adjoint_step_dot_product_periodic_rows(ora, nx, ny, T, kw):
+    """Periodic rows (the library's ny + 2 rows with rows 1 .. ny fluid, the reference's ny rows): a droplet across
+    the wrap in y; the same dot-product test, the wall angles taking no part."""
+    import torch
+    import paper_1501_05430_amd as P
+    rng = np.random.default_rng(ny)
+    ref = ora.Sim(nx, ny, T, periodic_y=True, **kw)
+    ref.init_droplets([nx / 2, nx / 5], [1.0, ny * 0.6], [min(nx, 2 * ny) * 0.3, 2.0])
+    ref.run(15)
+    f0 = ref.f.copy()
+    lib = lambda f: np.ascontiguousarray(np.moveaxis(f, 2, 0))   # [ny][nx][9] -> [9][ny][nx], every row fluid
+    sim = P.LBM(P.make_params(nx, ny + 2, T, boundary="periodic", enable_adjoint=True, **kw))
+    dev = sim.device
+    lam1 = rng.standard_normal((9, ny, nx))
+    t_l0 = torch.empty((9, ny, nx), dtype=torch.float64, device=dev)
+    t_th = torch.zeros((2, nx), dtype=torch.float64, device=dev)
+    t_G = torch.zeros(2, dtype=torch.float64, device=dev)
+    sim.adjoint_step(torch.tensor(lib(f0), device=dev), torch.tensor(lam1, device=dev), t_l0, t_th, t_G)
+    sim.stream.synchronize()
+    lam0, thb, Gb = t_l0.cpu().numpy(), t_th.cpu().numpy(), t_G.cpu().numpy()
+    sim.close()
+    assert np.all(thb == 0.0)
+    h = 1e-30
+    th = np.full(nx, np.pi / 2)
+    bad = []
+    for k in range(4):
+        v = rng.standard_normal(f0.shape) * 1e-3 if k < 3 else np.zeros(f0.shape)
+        vgf, vgp = (rng.standard_normal(), rng.standard_normal()) if k != 3 else (1.0, 0.0)
+        fc = ref.run_cplx(1, f0 + 1j * h * v, th, th, -1.0 + 1j * h * vgf, -1.0 + 1j * h * vgp)
+        lhs = float((lam1 * lib(fc.imag / h)).sum())
+        terms = np.array([(lam0 * lib(v)).sum(), Gb[0] * vgf, Gb[1] * vgp])
+        scale = abs(lhs) + np.abs(terms).sum() + 1e-300
+        if abs(lhs - terms.sum()) > 1e-10 * scale:
+            bad.append((k, lhs, float(terms.sum()), (lhs - terms.sum()) / scale))
+    assert not bad, bad
