@@ -14,7 +14,14 @@
 //      G_f_bar += F_bar . (F - F_body) / G_f;
 //   4. ghost rows: psi_bar_0 -> rho_bar_0 -> wetting transposed -> theta_bar and the boundary-row densities;
 //   5. psi transposed: rho_bar(y) = psi_bar dpsi/drho, G_psi_bar += psi_bar dpsi/dG_psi; dL/df_k += rho_bar.
+// The same order covers the other options of the forward step: the MRT collision of Eq. 15 (transposed in moment
+// space, collide_mrt_adj) with the source of Eq. 16-17, whose Q reads psi like the force does (Q_bar joins F_bar
+// in step 3; G_f_bar += Q_bar : Q / G_f); Martys-Chen walls (Eq. 14: psi_bar += +-(G_w/2) F_bar_y on the boundary
+// rows, no ghost rows to transpose); periodic rows (every neighbour a fluid row, no ghost rows).
 // Kinks (|T| of Eq. 19, the square root at 0, the clamps) take the sub-gradient 0.
+// Passes: ka_prep_rows and ka_ghost_fwd (forward values of the wall rows), ka_fused (steps 1-3 and 5 in one
+// walk over row strips), ka_ghost_adj (step 4), ka_wall_fix (step 4's boundary-row terms into lambda_n),
+// ka_finalize (the G partials).
 #include <hip/hip_runtime.h>
 #include <math.h>
 

@@ -169,3 +169,43 @@ def test_adjoint_step_dot_product_periodic_rows(ora, nx, ny, T, kw):
         if abs(lhs - terms.sum()) > 1e-10 * scale:
             bad.append((k, lhs, float(terms.sum()), (lhs - terms.sum()) / scale))
     assert not bad, bad
+
+
+def test_wall_angles_recovered_by_gradient_descent():
+    """The adjoint put to its use: from walls at 90 deg, Adam on the rollout gradient finds wall angles that
+    reproduce the density field of a 60 deg run (128 x 64, 0.7 T_c, semicircle R = 20, 1000 steps). Measured: the
+    loss falls from 3.90 to 0.016 in 20 iterations, where over the wetted columns (|x - 64| < 30) the angle averages
+    64.8 deg (columns under the droplet, which the density barely depends on, move less)."""
+    import math
+    import torch
+    import paper_1501_05430_amd as P
+    from paper_1501_05430_amd.autograd import rollout
+    nx, ny, steps = 128, 64, 1000
+    sim = P.LBM(P.make_params(nx, ny, 0.7, enable_adjoint=True))
+    sim.apply_wetting(math.pi / 2, math.pi / 2)
+    sim.init_droplet(nx / 2, 0.5, 20.0)
+    f0 = sim.populations(device=True)
+    sim.apply_wetting(np.full(nx, math.radians(60.0)), np.full(nx, math.pi / 2))
+    sim.set_populations(f0)
+    sim.step(steps)
+    target = sim.rho(device=True)[1:-1].clone()
+    tb = torch.full((nx,), math.pi / 2, dtype=torch.float64, requires_grad=True)
+    tt = torch.full((nx,), math.pi / 2, dtype=torch.float64)
+    opt = torch.optim.Adam([tb], lr=0.03)
+    losses, thetas = [], []
+    for _ in range(24):
+        opt.zero_grad()
+        rho = rollout(tb, tt, -1.0, sim, f0, steps, seg=100)
+        L = torch.linalg.norm(rho - target.to(rho.device))
+        L.backward()
+        losses.append(float(L.detach()))
+        thetas.append(np.degrees(tb.detach().numpy().copy()))
+        opt.step()
+        with torch.no_grad():
+            tb.clamp_(0.2, math.pi - 0.2)
+    sim.close()
+    best = int(np.argmin(losses))
+    wetted = thetas[best][34:94].mean()
+    print(f"\n  loss {losses[0]:.3f} -> {losses[best]:.4f} at iteration {best}; wetted-column mean {wetted:.2f} deg")
+    assert losses[best] < 0.05 * losses[0], losses
+    assert abs(wetted - 60.0) <= 5.0, wetted
