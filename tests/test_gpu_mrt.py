@@ -105,12 +105,14 @@ def test_mrt_with_equal_rates_matches_bgk(tau):
     assert 0 < err <= 1e-13 or err == 0, err
 
 
+@pytest.mark.parametrize("kw", [dict(tau=0.8, mrt=(1.1, 1.2, 1.3), kappa=0.5), dict(kappa=0.5)],
+                         ids=["mrt_kappa", "tau1_kappa"])
 @pytest.mark.parametrize("precision", ["f64", "f32", "f32_shifted"])
-def test_mirror_symmetry_bitwise(precision):
+def test_mirror_symmetry_bitwise(precision, kw):
     """A wall droplet symmetric about x = nx/2 and a free droplet symmetric about both mid-lines stay exactly
-    symmetric through the MRT collision and the source term."""
+    symmetric through the MRT collision and the source term, with general rates and with the paper's relaxation
+    matrix diag(0,1,...,1)."""
     import paper_1501_05430_amd as P
-    kw = dict(tau=0.8, mrt=(1.1, 1.2, 1.3), kappa=0.5)
     extra = P.fp32_options(0.85, precision)
     sim = P.LBM(P.make_params(200, 100, 0.85, precision=precision, **extra, **kw))
     sim.apply_wetting(math.radians(60.0), math.radians(60.0))
