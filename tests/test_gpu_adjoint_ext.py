@@ -16,6 +16,7 @@ CASES = {
     "kappa_eq19_sc": (33, 6, 0.75, dict(kappa=0.3, wet_iters=0, A=0.0)),
     "mrt_only_ny4": (64, 4, 0.75, dict(tau=1.3, mrt=(1.6, 1.5, 1.9), wet_iters=7)),
     "martys_chen": (40, 14, 0.75, dict(G_w=(-0.3, -0.2))),
+    "smallest_lattice": (2, 4, 0.75, dict(tau=0.9)),
     "martys_chen_mrt_kappa_pw10": (40, 14, 1.0, dict(piecewise=PW10, kappa=0.5, G_w=(-1.5, -1.2), tau=0.9,
                                                     mrt=(1.2, 1.4, 1.1), body_force=(1e-5, -2e-6))),
 }
