@@ -139,3 +139,28 @@ def test_sec3_near_wall_density_distortion():
     r = sim.rho()
     sim.close()
     assert abs(r[1, 0] - r[50, 0]) <= 1e-3 * r[50, 0], (r[1, 0], r[50, 0])
+
+
+def test_sec3_angle_depends_on_surface_tension():
+    """Fig. 4 (density ratio 10, Sec. 3.1's setup, 60 000 steps, settled): with the fluid-solid force the angle
+    moves with kappa, and not as Young's equation at fixed solid surface tensions would have it (cos theta
+    proportional to 1 / (1 - kappa)). Measured for kappa = 0.5 / 0.9 / 0.98: 129.9 / 107.9 / 98.9 deg at
+    G_w = -1.1, 103.7 / 84.2 / 75.7 at -1.43 (the paper: about 90 deg at kappa = 0.9), 66.4 / 52.6 / 51.3 at -2.1.
+    The geometric wall holds its angle within 5 deg over the same kappa (test_gpu_mrt.py, Fig. 9)."""
+    import math
+    import paper_1501_05430_amd as P
+    th = {}
+    for gw in (-1.1, -1.43, -2.1):
+        for kappa in (0.5, 0.9, 0.98):
+            sim = P.LBM(P.make_params(200, 100, 1.0, piecewise=PW[10], kappa=kappa, boundary="martys_chen",
+                                      G_w=(gw, 0.0), check_every=1000))
+            sim.init_droplet(100.0, 0.5, 30.0)
+            sim.step(60000)
+            th[gw, kappa] = math.degrees(sim.measure_contact_angle((0, 200, 1, 80), 0)[0])
+            sim.close()
+    print("\n  " + ", ".join(f"G_w={g} kappa={k}: {v:.2f}" for (g, k), v in th.items()))
+    for gw in (-1.1, -1.43, -2.1):
+        assert th[gw, 0.5] - th[gw, 0.98] > 10.0, (gw, th)       # less surface tension, smaller angle
+    assert abs(th[-1.43, 0.9] - 90.0) <= 10.0, th
+    c = [math.cos(math.radians(th[-1.43, k])) for k in (0.5, 0.98)]
+    assert c[0] < 0.0 < c[1]                                      # the sign flips: no 1 / (1 - kappa) scaling
