@@ -189,11 +189,12 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
     }
 
 
-def adjoint_rate(case, calls=30):
+def adjoint_rate(case, calls=30, **kw):
     """lbm_adjoint_step on the same lattice (FP64 state, a seeded random cotangent): time per reverse step. Its
-    unavoidable traffic is 216 B per node: f_n and lambda_{n+1} read, lambda_n written, 9 FP64 values each."""
+    unavoidable traffic is 216 B per node: f_n and lambda_{n+1} read, lambda_n written, 9 FP64 values each. kw:
+    further lattice options (EOS, collision, kappa)."""
     import torch
-    sim = make_sim(case, "f64", check_every=0, enable_adjoint=True)
+    sim = make_sim(case, "f64", check_every=0, enable_adjoint=True, **kw)
     sim.step(20)
     f = sim.populations(device=True)
     g = torch.Generator(device=f.device)
@@ -321,6 +322,9 @@ def main():
             "adjoint_fp64_same_lattice": adjoint_rate(case),
             "piecewise_eos_ratio1000_same_lattice": piecewise_rate(case),
             "paper_setting_ratio1000_kappa05_same_lattice": piecewise_rate(case, kappa=0.5),
+            # the reverse step in the paper's setting (MRT form with the surface-tension source)
+            "adjoint_paper_setting_same_lattice": adjoint_rate(case, piecewise=(0.2, -0.01, 0.33333, 1.0, 1000.0),
+                                                               kappa=0.5),
         }
         out["extras"]["adjoint_fp64_same_lattice"]["vs_forward_fp64"] = round(
             out["extras"]["adjoint_fp64_same_lattice"]["mlups"] / out["extras"]["fp64_same_lattice"]["mlups"], 3)
