@@ -189,14 +189,16 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
     }
 
 
-def adjoint_rate(case, calls=30, **kw):
+def adjoint_rate(case, calls=30, dtype="f64", **kw):
     """lbm_adjoint_step on the same lattice (FP64 state, a seeded random cotangent): time per reverse step. Its
-    unavoidable traffic is 216 B per node: f_n and lambda_{n+1} read, lambda_n written, 9 FP64 values each. kw:
+    unavoidable traffic is 216 B per node (108 with dtype="f32"): f_n and lambda_{n+1} read, lambda_n written. kw:
     further lattice options (EOS, collision, kappa)."""
     import torch
     sim = make_sim(case, "f64", check_every=0, enable_adjoint=True, **kw)
     sim.step(20)
     f = sim.populations(device=True)
+    if dtype == "f32":  # lbm_adjoint_step_f32: FP32 state and adjoints (FP64 arithmetic)
+        f = f.float()
     g = torch.Generator(device=f.device)
     g.manual_seed(1501)
     lam1 = torch.randn(f.shape, generator=g, device=f.device, dtype=f.dtype)
@@ -215,8 +217,9 @@ def adjoint_rate(case, calls=30, **kw):
     ms = e0.elapsed_time(e1) / calls
     finite = bool(torch.isfinite(lam0).all().item())
     sim.close()
+    nbytes = 216 if dtype == "f64" else 108
     return {"ms_per_step": round(ms, 4), "mlups": round(case.fluid_nodes / ms / 1e3, 1),
-            "gbs_alg": round(216 * case.fluid_nodes / ms / 1e6, 1), "finite": finite}
+            "gbs_alg": round(nbytes * case.fluid_nodes / ms / 1e6, 1), "finite": finite}
 
 
 def piecewise_rate(case, steps=2000, kappa=0.0):
@@ -320,6 +323,7 @@ def main():
                                   "gbs_alg": round(144 * nodes * 1000 / ms64 / 1e6, 1), "stable": st64},
             "batched_256": batched_vs_plain(),
             "adjoint_fp64_same_lattice": adjoint_rate(case),
+            "adjoint_fp32_storage_same_lattice": adjoint_rate(case, dtype="f32"),
             "piecewise_eos_ratio1000_same_lattice": piecewise_rate(case),
             "paper_setting_ratio1000_kappa05_same_lattice": piecewise_rate(case, kappa=0.5),
             # the reverse step in the paper's setting (MRT form with the surface-tension source)

@@ -211,6 +211,13 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
 int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const double* d_lambda_np1,
                      double* d_lambda_n, double* d_theta_bar, double* d_G_bar);
 
+/* lbm_adjoint_step with the state and the adjoints in FP32 (device arrays of the same [9][ny-2][nx] layout): the
+ * arithmetic is the same FP64 evaluation, only the state is read from and lambda_n written to FP32, which halves
+ * the reverse step's unavoidable traffic (108 B per fluid node). d_theta_bar and d_G_bar stay FP64 and accumulate
+ * as above. Same preconditions and errors as lbm_adjoint_step. */
+int lbm_adjoint_step_f32(lbm_ctx* c, int32_t inst, const float* d_state_n, const float* d_lambda_np1,
+                         float* d_lambda_n, double* d_theta_bar, double* d_G_bar);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);
 

@@ -78,12 +78,13 @@ __device__ inline void node_rho_psi(const InstDesc& d, const double (&fl)[9], do
   p = psi_f64(d, r, cl);
 }
 
-__device__ inline void prep_node(const InstDesc& d, const double* __restrict__ f, int64_t n, int nx, int x, int y,
+template <class T>
+__device__ inline void prep_node(const InstDesc& d, const T* __restrict__ f, int64_t n, int nx, int x, int y,
                                  AdjScratch& sc) {
   const unsigned k = (unsigned)((y - 1) * nx + x);  // node counts are below 2^31 (lbm_create checks)
   double fl[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) fl[i] = f[i * n + k];
+  for (int i = 0; i < 9; ++i) fl[i] = (double)f[i * n + k];
   double r, p;
   node_rho_psi(d, fl, r, p);
   Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
@@ -92,8 +93,9 @@ __device__ inline void prep_node(const InstDesc& d, const double* __restrict__ f
 }
 
 // density and psi into the scratch field of the four wall-adjacent rows (read by the ghost rows and their adjoint)
+template <class T>
 __global__ __launch_bounds__(AB) void ka_prep_rows(const InstDesc* __restrict__ descs, int inst,
-                                                   const double* __restrict__ f, AdjScratch sc) {
+                                                   const T* __restrict__ f, AdjScratch sc) {
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int t = (int)(blockIdx.x * AB + threadIdx.x);
@@ -341,10 +343,11 @@ __device__ inline void force_vals(const InstDesc& d, double pmL, double pm, doub
 
 // EXT: the MRT collision with the source of Eq. 16-17 (Q_bar joins F_bar in the ring) and the fluid-solid force of
 // Eq. 14 on the boundary rows; without it only the BGK collision with geometric walls is compiled.
-template <bool EXT>
+// T: storage type of the state and of lambda (double, or float for lbm_adjoint_step_f32); the arithmetic is FP64.
+template <bool EXT, class T>
 __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
-                                                  const double* __restrict__ f, const double* __restrict__ lam1,
-                                                  double* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
+                                                  const T* __restrict__ f, const T* __restrict__ lam1,
+                                                  T* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
                                                   int ntasks) {
   constexpr int NR = EXT ? 5 : 2;  // per node in the ring: F_bar (x, y), then Q_bar (xx, yy, xy)
   __shared__ double ring[3][NR][FL];
@@ -371,12 +374,18 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
     const int x = act ? wrapx(x0 - 2 + l, nx) : 0;
     const int yc0 = py ? y0 - 1 : max(1, y0 - 1), yc1 = py ? ylast + 1 : min(ny - 2, ylast + 1);
     auto fluid = [&](int y) { return py || (y >= 1 && y <= ny - 2); };
-    auto load_f = [&](int y, double (&fl)[9]) {
+    // loads keep the storage type: a prefetched row is widened only where the window slides, so nothing waits
+    // for it earlier (a conversion right after the load would)
+    auto load_f = [&](int y, T (&fl)[9]) {
       const unsigned k = (unsigned)((wy(y) - 1) * nx + x);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fl[i] = act ? f[i * n + k] : 0.0;
+      for (int i = 0; i < 9; ++i) fl[i] = act ? f[i * n + k] : (T)0;
     };
-    auto load_lam = [&](int y, double (&ls)[9]) {
+    auto widen = [&](const T (&a)[9], double (&b)[9]) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) b[i] = (double)a[i];
+    };
+    auto load_lam = [&](int y, T (&ls)[9]) {
       const int yw = wy(y);
       const unsigned k = (unsigned)((yw - 1) * nx + x);
 #pragma unroll
@@ -384,29 +393,39 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
         int yd = yw + kEY[i];
         const bool wall = !py && (yd < 1 || yd > ny - 2);
         if (py) yd = wy(yd);
-        ls[i] = !act ? 0.0
-                     : (wall ? lam1[kOPP[i] * n + k]
-                             : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))]);
+        ls[i] = !act ? (T)0
+                     : (wall ? lam1[kOPP[i] * n + k] : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))]);
       }
     };
     // window at the stage C row yc: psi of rows yc-2 (a), yc-1 (b), yc (c), yc+1 (e), rho of rows yc-1 (rb),
     // yc (rc), yc+1 (re); populations of rows yc (fA), yc+1 (fB); pg the ghost row's psi when row yc+1 is one
     double pa = 0.0, pb = 0.0, pc = 0.0, pe = 0.0, rb = 0.0, rc = 0.0, re = 0.0, pg = 0.0;
-    double fA[9], fB[9], fN[9], lsA[9], lsN[9], lcur[9];
+    double fA[9], fB[9], lsA[9], lcur[9];
+    T fN[9], lsN[9], tt[9];  // fN, lsN: the prefetched row, in the storage type
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fB[i] = fN[i] = lsN[i] = lcur[i] = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      fB[i] = lcur[i] = 0.0;
+      fN[i] = lsN[i] = (T)0;
+    }
     if (fluid(yc0 - 1)) {
       double ft[9];
-      load_f(yc0 - 1, ft);
+      load_f(yc0 - 1, tt);
+      widen(tt, ft);
       node_rho_psi(d, ft, rb, pb);
     } else {
       pb = act ? P.at(x, yc0 - 1) : 0.0;  // ghost row
     }
-    load_f(yc0, fA);
+    load_f(yc0, tt);
+    widen(tt, fA);
     node_rho_psi(d, fA, rc, pc);
-    if (fluid(yc0 + 1)) load_f(yc0 + 1, fB);
-    else pg = act ? P.at(x, yc0 + 1) : 0.0;
-    load_lam(yc0, lsA);
+    if (fluid(yc0 + 1)) {
+      load_f(yc0 + 1, tt);
+      widen(tt, fB);
+    } else {
+      pg = act ? P.at(x, yc0 + 1) : 0.0;
+    }
+    load_lam(yc0, tt);
+    widen(tt, lsA);
     // left / right neighbours of a per-lane value (meaningful on lanes 1 .. w+2)
     auto lr = [&](double v, double& L, double& Rr) {
       L = __shfl(v, l > 0 ? l - 1 : 0, FL);
@@ -451,7 +470,7 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
       const double rbar = acc * dpsi_drho(d, rb, pb);
       const unsigned k = (unsigned)((wy(ys) - 1) * nx + x);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) lam0[i * n + k] = ldir[i][l] + rbar;
+      for (int i = 0; i < 9; ++i) lam0[i * n + k] = (T)(ldir[i][l] + rbar);
     };
     for (int yc = yc0; yc <= yc1; ++yc) {
       // psi and rho of row yc+1 from its populations (loaded one iteration ago), or the ghost row's psi
@@ -525,8 +544,8 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
       for (int i = 0; i < 9; ++i) {
         ldir[i][l] = lcur[i];  // same lane reads it back at the next stage S
         fA[i] = fB[i];
-        fB[i] = fN[i];
-        lsA[i] = lsN[i];
+        fB[i] = (double)fN[i];
+        lsA[i] = (double)lsN[i];
       }
     }
     // the top wall's boundary row: no stage C row above it (row ny-1 is the ghost row, F_bar absent there);
@@ -550,8 +569,9 @@ __global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __re
 
 // The wetting's boundary-row adjoints (from ka_ghost_adj) into lambda_n: rows 1, 2 (bottom wall) and ny-2, ny-3
 // (top wall), each fluid row once, every population of the node (rho = sum_i f_i).
+template <class T>
 __global__ __launch_bounds__(AB) void ka_wall_fix(const InstDesc* __restrict__ descs, int inst,
-                                                  double* __restrict__ lam0, AdjScratch sc) {
+                                                  T* __restrict__ lam0, AdjScratch sc) {
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int64_t n = (int64_t)nx * (ny - 2);
@@ -573,7 +593,7 @@ __global__ __launch_bounds__(AB) void ka_wall_fix(const InstDesc* __restrict__ d
   }
   const unsigned k = (unsigned)((y - 1) * nx + x);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) lam0[i * n + k] += rb;
+  for (int i = 0; i < 9; ++i) lam0[i * n + k] = (T)((double)lam0[i * n + k] + rb);
 }
 
 // Fold of the partials into G_bar by one block: each thread sums a fixed strided subset in order, then a fixed
@@ -599,9 +619,10 @@ __global__ __launch_bounds__(AB) void ka_finalize(AdjScratch sc, int nb_fluid, i
 
 int adjoint_partials_needed() { return 3 * kAdjBlocks; }
 
-hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc,
-                          const double* f_n, const double* lam_np1, double* lam_n, double* theta_bar, double* G_bar,
-                          hipStream_t s) {
+namespace {
+template <class T>
+hipError_t launch_adjoint_t(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc, const T* f_n,
+                            const T* lam_np1, T* lam_n, double* theta_bar, double* G_bar, hipStream_t s) {
   const unsigned gghost = (unsigned)((2 * h.nx + AB - 1) / AB);
   if (gghost > (unsigned)kAdjBlocks) return hipErrorInvalidValue;
   // fused pass: column blocks of at most FL - 4 columns (balanced), and row strips sized so that the tasks fit
@@ -621,23 +642,35 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
   const unsigned gfused = (unsigned)std::min(ntasks, kAdjBlocks);
   const bool walls = h.periodic_y == 0;  // periodic rows have no ghost rows and no wetting
   if (walls) {
-    hipLaunchKernelGGL(ka_prep_rows, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n,
+    hipLaunchKernelGGL(ka_prep_rows<T>, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n,
                        sc);
     hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
   }
   if (h.mrt || h.wall_mc)
-    hipLaunchKernelGGL(ka_fused<true>, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
+    hipLaunchKernelGGL((ka_fused<true, T>), dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
                        H, ntasks);
   else
-    hipLaunchKernelGGL(ka_fused<false>, dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
+    hipLaunchKernelGGL((ka_fused<false, T>), dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
                        H, ntasks);
   if (walls) {
     hipLaunchKernelGGL(ka_ghost_adj, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc, theta_bar);
-    hipLaunchKernelGGL(ka_wall_fix, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, lam_n,
+    hipLaunchKernelGGL(ka_wall_fix<T>, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, lam_n,
                        sc);
   }
   hipLaunchKernelGGL(ka_finalize, dim3(1), dim3(AB), 0, s, sc, (int)gfused, walls ? (int)gghost : 0, G_bar);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc, bool f32,
+                          const void* f_n, const void* lam_np1, void* lam_n, double* theta_bar, double* G_bar,
+                          hipStream_t s) {
+  if (f32)
+    return launch_adjoint_t<float>(d_desc, h, inst, sc, (const float*)f_n, (const float*)lam_np1, (float*)lam_n,
+                                   theta_bar, G_bar, s);
+  return launch_adjoint_t<double>(d_desc, h, inst, sc, (const double*)f_n, (const double*)lam_np1, (double*)lam_n,
+                                  theta_bar, G_bar, s);
 }
 
 }  // namespace lbm

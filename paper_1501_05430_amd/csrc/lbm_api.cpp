@@ -1047,8 +1047,11 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const double* d_lambda_np1,
-                     double* d_lambda_n, double* d_theta_bar, double* d_G_bar) {
+}  // extern "C"
+
+namespace {
+int adjoint_step(lbm_ctx* c, int32_t inst, bool f32, const void* d_state_n, const void* d_lambda_np1,
+                 void* d_lambda_n, double* d_theta_bar, double* d_G_bar) {
   CHECK_INST(c, inst);
   if (!d_state_n || !d_lambda_np1 || !d_lambda_n || !d_theta_bar || !d_G_bar)
     return fail(LBM_E_INVALID, "NULL buffer");
@@ -1069,9 +1072,22 @@ int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const do
   sc.part = (double*)(base + 4 * field + align256(sizeof(double) * 2 * nx) + align256(sizeof(double) * 8 * nx) +
                       align256(sizeof(double) * 6 * nx));
   if (2 * nx > 1024 * 256) return fail(LBM_E_UNSUPPORTED, "adjoint: nx too large");
-  HIP_TRY(launch_adjoint(c->d_desc(), c->hdesc[inst], inst, sc, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar,
-                         d_G_bar, c->stream));
+  HIP_TRY(launch_adjoint(c->d_desc(), c->hdesc[inst], inst, sc, f32, d_state_n, d_lambda_np1, d_lambda_n,
+                         d_theta_bar, d_G_bar, c->stream));
   return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const double* d_lambda_np1,
+                     double* d_lambda_n, double* d_theta_bar, double* d_G_bar) {
+  return adjoint_step(c, inst, false, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar, d_G_bar);
+}
+
+int lbm_adjoint_step_f32(lbm_ctx* c, int32_t inst, const float* d_state_n, const float* d_lambda_np1,
+                         float* d_lambda_n, double* d_theta_bar, double* d_G_bar) {
+  return adjoint_step(c, inst, true, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar, d_G_bar);
 }
 
 }  // extern "C"

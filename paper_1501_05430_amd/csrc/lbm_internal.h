@@ -102,9 +102,10 @@ struct AdjScratch {
   double* part;   // [adjoint_partials_needed()] reduction partials for G_bar
 };
 int adjoint_partials_needed();
-hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc,
-                          const double* f_n, const double* lam_np1, double* lam_n, double* theta_bar,
-                          double* G_bar, hipStream_t s);
+// f32: the state and lambda are FP32 (else FP64); theta_bar and G_bar are FP64 either way
+hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc, bool f32,
+                          const void* f_n, const void* lam_np1, void* lam_n, double* theta_bar, double* G_bar,
+                          hipStream_t s);
 
 constexpr int kMeasureBlocks = 512;
 constexpr int kMeasureMoments = 10;

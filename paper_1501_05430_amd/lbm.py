@@ -249,14 +249,19 @@ class LBM:
         return out[0], out[1], out[2], out[3], int(out[4])
 
     def adjoint_step(self, f_n, lam_np1, lam_n, theta_bar, G_bar, inst=0):
-        """lam_n = (df_{n+1}/df_n)^T lam_np1; theta_bar [2, nx] and G_bar [2] accumulate (device FP64 tensors)."""
+        """lam_n = (df_{n+1}/df_n)^T lam_np1; theta_bar [2, nx] and G_bar [2] accumulate (device FP64 tensors).
+        f_n, lam_np1 and lam_n are all FP64 (lbm_adjoint_step) or all FP32 (lbm_adjoint_step_f32)."""
         import torch
-        for t in (f_n, lam_np1, lam_n, theta_bar, G_bar):
+        dt = f_n.dtype
+        assert dt in (torch.float64, torch.float32)
+        for t in (f_n, lam_np1, lam_n):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == dt
+        for t in (theta_bar, G_bar):
             assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        check(self.lib.lbm_adjoint_step(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),
-                                        C.c_void_p(lam_n.data_ptr()), C.c_void_p(theta_bar.data_ptr()),
-                                        C.c_void_p(G_bar.data_ptr())))
+        fn = self.lib.lbm_adjoint_step if dt == torch.float64 else self.lib.lbm_adjoint_step_f32
+        check(fn(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),
+                 C.c_void_p(lam_n.data_ptr()), C.c_void_p(theta_bar.data_ptr()), C.c_void_p(G_bar.data_ptr())))
         self._hand_over()
 
     def _hand_over(self):

@@ -210,3 +210,90 @@ def test_wall_angles_recovered_by_gradient_descent():
     print(f"\n  loss {losses[0]:.3f} -> {losses[best]:.4f} at iteration {best}; wetted-column mean {wetted:.2f} deg")
     assert losses[best] < 0.05 * losses[0], losses
     assert abs(wetted - 60.0) <= 5.0, wetted
+
+
+def _adjoint_pair(sim, f64, lam1_32, nx):
+    """The reverse step through both entry points at the same FP32-representable state and cotangent."""
+    import torch
+    dev = f64.device
+    out = []
+    for dt in (torch.float64, torch.float32):
+        l0 = torch.empty(lam1_32.shape, dtype=dt, device=dev)
+        th = torch.zeros((2, nx), dtype=torch.float64, device=dev)
+        G = torch.zeros(2, dtype=torch.float64, device=dev)
+        sim.adjoint_step(f64.to(dt).contiguous(), lam1_32.to(dt).contiguous(), l0, th, G)
+        sim.stream.synchronize()
+        out.append((l0.cpu().numpy(), th.cpu().numpy(), G.cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("kw,periodic", [(dict(), False), (dict(tau=0.8, mrt=(1.2, 1.4, 1.1), kappa=0.5), False),
+                                         (dict(boundary="martys_chen", G_w=(-0.3, -0.2)), False),
+                                         (dict(kappa=0.3), True)], ids=["bgk", "mrt_kappa", "martys_chen", "periodic"])
+def test_fp32_entry_point_rounds_only_the_output(kw, periodic):
+    """lbm_adjoint_step_f32 evaluates the same FP64 arithmetic on the FP32 state and cotangent: theta_bar and G_bar
+    equal the FP64 entry point's bit for bit (given the same FP32-representable inputs), and lambda_n is the FP64
+    result rounded to FP32 (one extra rounding on the four wall rows that receive the wetting terms: within 2 ulp
+    of their largest value)."""
+    import math
+    import torch
+    import paper_1501_05430_amd as P
+    nx, ny = 96, 40 if not periodic else 42
+    if periodic:
+        kw = dict(kw, boundary="periodic")
+    sim = P.LBM(P.make_params(nx, ny, 0.75, enable_adjoint=True, **kw))
+    rng = np.random.default_rng(3)
+    if not periodic:
+        sim.apply_wetting(np.radians(rng.uniform(40, 140, nx)), np.radians(rng.uniform(40, 140, nx)))
+    sim.init_droplet([48.0, 20.0], [0.5 if not periodic else 20.0, 25.0], [16.0, 4.0])
+    sim.step(30)
+    f64 = sim.populations(device=True).float().double()
+    lam1 = torch.tensor(rng.standard_normal(f64.shape), dtype=torch.float32, device=f64.device)
+    (l64, th64, G64), (l32, th32, G32) = _adjoint_pair(sim, f64, lam1, nx)
+    sim.close()
+    assert np.array_equal(th64, th32) and np.array_equal(G64, G32)
+    rounded = l64.astype(np.float32)
+    rows = np.ones(ny - 2, bool)
+    if not periodic:
+        rows[[0, 1, ny - 4, ny - 3]] = False      # fluid rows 1, 2, ny-3, ny-2
+    assert np.array_equal(l32[:, rows], rounded[:, rows])
+    if not periodic:
+        # the wall rows add the wetting terms to the already rounded value: a second rounding of the sum
+        w = rounded[:, ~rows]
+        assert np.abs(l32[:, ~rows] - w).max() <= 2 * np.spacing(np.float32(np.abs(w).max()))
+
+
+def test_fp32_reverse_rollout_tracks_fp64():
+    """200 reverse steps along an FP32 forward trajectory (128 x 64, 0.7 T_c, heterogeneous walls, cotangent of a
+    weighted density sum): the wall-angle gradient accumulated through the FP32 entry point stays within 1e-5 of
+    the one through the FP64 entry point (lambda is rounded to FP32 once per step)."""
+    import math
+    import torch
+    import paper_1501_05430_amd as P
+    nx, ny, steps = 128, 64, 200
+    rng = np.random.default_rng(11)
+    tb, tt = np.radians(90 + rng.normal(0, 10, nx)), np.radians(90 + rng.normal(0, 10, nx))
+    sim = P.LBM(P.make_params(nx, ny, 0.7, precision="f32", enable_adjoint=True, **P.fp32_options(0.7, "f32")))
+    sim.apply_wetting(tb, tt)
+    sim.init_droplet(nx / 2, 0.5, 20.0)
+    states = []
+    for _ in range(steps):
+        states.append(sim.populations(device=True).float())
+        sim.step(1)
+    wgt = torch.tensor(rng.standard_normal((ny - 2, nx)), device=states[0].device)
+    res = {}
+    for dt in (torch.float64, torch.float32):
+        lam = wgt.to(dt).expand(9, ny - 2, nx).contiguous()
+        th = torch.zeros((2, nx), dtype=torch.float64, device=lam.device)
+        G = torch.zeros(2, dtype=torch.float64, device=lam.device)
+        nxt = torch.empty_like(lam)
+        for n in range(steps - 1, -1, -1):
+            sim.adjoint_step(states[n].to(dt).contiguous(), lam, nxt, th, G)
+            lam, nxt = nxt, lam
+        sim.stream.synchronize()
+        res[dt] = th.cpu().numpy()
+    sim.close()
+    a, b = res[torch.float32], res[torch.float64]
+    err = np.abs(a - b).max() / np.abs(b).max()
+    print(f"\n  FP32 vs FP64 reverse rollout: max |dtheta_bar| / max |theta_bar| = {err:.2e}")
+    assert np.abs(b).max() > 0 and err <= 1e-5, err
