@@ -3,7 +3,9 @@
 rho_N = Rollout(theta_bottom, theta_top, G) runs N steps from a fixed initial state with per-column wall angles
 (radians) and returns the fluid-row density [ny-2, nx] after the last step. backward() walks the steps in reverse
 with lbm_adjoint_step: the forward pass keeps an FP64 checkpoint of the populations every `seg` steps, and each
-segment is recomputed (its states kept on the device) before its adjoint steps run.
+segment is recomputed (its states kept on the device) before its adjoint steps run. For an instance with FP32
+storage the segment's states and the adjoints are kept in FP32 and go through lbm_adjoint_step_f32 (FP64
+arithmetic, lambda rounded to FP32 once per step), unless fp32_adjoint=False asks for the FP64 entry point.
 
 G enters the model twice (the force prefactor of Eq. 9 and the G inside the psi inversion of Eq. 10); the
 gradient returned for G is their sum, the total derivative, which is zero for this model. The two parts of the
@@ -19,7 +21,7 @@ class Rollout(torch.autograd.Function):
     last_G_parts = (0.0, 0.0)
 
     @staticmethod
-    def forward(ctx, theta_bottom, theta_top, G, sim, f0, nsteps, seg):
+    def forward(ctx, theta_bottom, theta_top, G, sim, f0, nsteps, seg, fp32_adjoint=None):
         assert isinstance(sim, LBM) and sim.params[0].enable_adjoint, "needs an LBM created with enable_adjoint"
         assert abs(float(G) - sim.params[0].G) == 0.0, "G must equal the instance's G"
         nsteps, seg = int(nsteps), int(seg)
@@ -35,6 +37,7 @@ class Rollout(torch.autograd.Function):
         rho = sim.rho(device=True)[1:-1].clone()
         sim.stream.synchronize()
         ctx.sim, ctx.nsteps, ctx.seg, ctx.checkpoints = sim, nsteps, seg, checkpoints
+        ctx.f32 = (sim.params[0].precision != 0) if fp32_adjoint is None else bool(fp32_adjoint)
         ctx.theta = (theta_bottom.detach().cpu().numpy(), theta_top.detach().cpu().numpy())
         return rho.to(theta_bottom.device)
 
@@ -43,8 +46,9 @@ class Rollout(torch.autograd.Function):
         sim, nsteps, seg = ctx.sim, ctx.nsteps, ctx.seg
         p = sim.params[0]
         dev = sim.device
+        dtype = torch.float32 if ctx.f32 else torch.float64
         with torch.cuda.stream(sim.stream):
-            lam = grad_rho.detach().to(dev, torch.float64).contiguous().unsqueeze(0).expand(9, -1, -1).contiguous()
+            lam = grad_rho.detach().to(dev, dtype).contiguous().unsqueeze(0).expand(9, -1, -1).contiguous()
             lam_prev = torch.empty_like(lam)
             theta_bar = torch.zeros((2, p.nx), dtype=torch.float64, device=dev)
             G_bar = torch.zeros(2, dtype=torch.float64, device=dev)
@@ -55,7 +59,7 @@ class Rollout(torch.autograd.Function):
             sim.set_populations(ctx.checkpoints[si])
             states = []
             for j in range(k):
-                states.append(sim.populations(device=True))
+                states.append(sim.populations(device=True).to(dtype))
                 if j + 1 < k:
                     sim.step(1)
             for j in reversed(range(k)):
@@ -67,8 +71,10 @@ class Rollout(torch.autograd.Function):
         tb = theta_bar.cpu()
         ctx.checkpoints = None
         return (tb[0].to(grad_rho.device), tb[1].to(grad_rho.device),
-                torch.tensor(float(gb[0] + gb[1]), dtype=torch.float64), None, None, None, None)
+                torch.tensor(float(gb[0] + gb[1]), dtype=torch.float64), None, None, None, None, None)
 
 
-def rollout(theta_bottom, theta_top, G, sim, f0, nsteps, seg=100):
-    return Rollout.apply(theta_bottom, theta_top, torch.as_tensor(G, dtype=torch.float64), sim, f0, nsteps, seg)
+def rollout(theta_bottom, theta_top, G, sim, f0, nsteps, seg=100, fp32_adjoint=None):
+    """fp32_adjoint: None follows the instance's storage precision; True / False force the FP32 / FP64 entry point."""
+    return Rollout.apply(theta_bottom, theta_top, torch.as_tensor(G, dtype=torch.float64), sim, f0, nsteps, seg,
+                         fp32_adjoint)

@@ -177,8 +177,9 @@ def rollout_grad(case, sim, f0, target):
 
 @pytest.mark.parametrize("precision", ["f32", "f32_shifted"])
 def test_c5_gradient_of_fp32_runs_tracks_fp64(c5, precision):
-    """FP32 forward runs: the adjoint linearises the step (in FP64) around the FP32 trajectory; its gradient stays
-    close to the FP64 run's, the distance set by how far the two trajectories drift apart."""
+    """FP32 forward runs: the rollout's adjoint (the FP32 storage form, FP64 arithmetic) linearises the step
+    around the FP32 trajectory; its gradient stays close to the FP64 run's, the distance set by how far the two
+    trajectories drift apart."""
     import paper_1501_05430_amd as P
     case, sim64, f0, target = c5
     L64, g64 = rollout_grad(case, sim64, f0, target)
