@@ -48,3 +48,27 @@ def test_mixed_feature_batch_equals_single_contexts_bitwise(precision):
         assert np.isfinite(a).all(), i
         assert np.array_equal(a, b), (i, np.abs(a - b).max())
     batch.close()
+
+
+def test_mixed_feature_batch_matches_reference(ora):
+    """The same batched launch (FP64) against the CPU reference, instance by instance, after 200 steps: 1e-12."""
+    import paper_1501_05430_amd as P
+    batch = P.LBM([params(s, "f64") for s in SPECS])
+    for i, s in enumerate(SPECS):
+        prepare(batch, s, inst=i)
+    batch.step(200, inst=-1)
+    for i, s in enumerate(SPECS):
+        kw = {k: v for k, v in s["kw"].items() if k != "boundary"}
+        periodic = s["kw"].get("boundary") == "periodic"
+        ny = s["ny"] - 2 if periodic else s["ny"]
+        th = s["walls"] or (90.0, 90.0)
+        ref = ora.Sim(s["nx"], ny, s["T"], theta_bottom=math.radians(th[0]), theta_top=math.radians(th[1]),
+                      periodic_y=periodic, **kw)
+        x, y, R = s["drop"]
+        ref.init_droplets([x], [y - 1.0 if periodic else y], [R])
+        ref.run(200)
+        f_ref = np.moveaxis(ref.f if periodic else ref.f[1:-1], 2, 0)
+        f = batch.populations(inst=i)
+        err = np.abs(f - f_ref).max() / np.abs(f_ref).max()
+        assert err <= 1e-12, (i, err)
+    batch.close()
