@@ -133,3 +133,27 @@ def test_adjoint_at_the_largest_lattice():
     assert bool(torch.isfinite(first[0]).all())
     assert torch.equal(lam0, 2.0 * first[0]) and torch.equal(thb, 2.0 * first[1])
     sim.close()
+
+
+def test_density_above_the_psi_cap_is_clamped_and_counted(ora):
+    """A droplet started above the largest density with real psi (0.5 against 0.458 at 0.85 T_c): psi is clamped
+    at 0 there and the ghost densities at rho_cap, and the device checks (every step) count exactly the clamps the
+    reference counts (1058 fluid and 162 ghost over 20 steps, the density then relaxing below the cap), with the
+    state still matching the reference."""
+    import paper_1501_05430_amd as P
+    nx, ny = 96, 40
+    th = np.radians(np.linspace(40.0, 140.0, nx))
+    ref = ora.Sim(nx, ny, 0.85, theta_bottom=th, theta_top=th[::-1].copy())
+    ref.init_droplets([48.0], [0.5], [14.0], rho_l=0.5)
+    ref.run(20)
+    sim = P.LBM(P.make_params(nx, ny, 0.85, check_every=1))
+    sim.apply_wetting(th, th[::-1].copy())
+    sim.init_droplet(48.0, 0.5, 14.0, rho_l=0.5)
+    sim.step(20)
+    d = sim.diag()
+    f_ref = oracle_pops(ref)
+    err = np.abs(sim.populations() - f_ref).max() / np.abs(f_ref).max()
+    sim.close()
+    assert ref.counters[1] > 0 and ref.counters[0] > 0
+    assert d["psi_clamps"] == ref.counters[1] and d["ghost_clamps"] == ref.counters[0], (d, ref.counters)
+    assert d["nonfinite"] == 0 and err <= 1e-12, err
