@@ -236,6 +236,7 @@ class LBM:
 
     def set_state(self, state, inst=0):
         import torch
+        assert state.is_cuda and state.is_contiguous() and state.dtype == torch.uint8
         assert state.numel() == self.state_bytes(inst)
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         check(self.lib.lbm_set_state(self.ctx, inst, C.c_void_p(state.data_ptr())))
@@ -254,10 +255,11 @@ class LBM:
         import torch
         dt = f_n.dtype
         assert dt in (torch.float64, torch.float32)
-        for t in (f_n, lam_np1, lam_n):
-            assert t.is_cuda and t.is_contiguous() and t.dtype == dt
-        for t in (theta_bar, G_bar):
-            assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64
+        p = self.params[inst]
+        for t in (f_n, lam_np1, lam_n):   # the library takes raw pointers: sizes are checked here
+            assert t.is_cuda and t.is_contiguous() and t.dtype == dt and t.numel() == 9 * (p.ny - 2) * p.nx
+        for t, size in ((theta_bar, 2 * p.nx), (G_bar, 2)):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.numel() == size
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         fn = self.lib.lbm_adjoint_step if dt == torch.float64 else self.lib.lbm_adjoint_step_f32
         check(fn(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),

@@ -157,3 +157,23 @@ def test_density_above_the_psi_cap_is_clamped_and_counted(ora):
     assert ref.counters[1] > 0 and ref.counters[0] > 0
     assert d["psi_clamps"] == ref.counters[1] and d["ghost_clamps"] == ref.counters[0], (d, ref.counters)
     assert d["nonfinite"] == 0 and err <= 1e-12, err
+
+
+def test_binding_refuses_wrong_sizes_before_the_library():
+    """The C-ABI takes raw device pointers, so the binding checks sizes: a cotangent of the wrong size or a
+    host-side state buffer is refused before anything reaches the GPU."""
+    import torch
+    import paper_1501_05430_amd as P
+    sim = P.LBM(P.make_params(20, 10, 0.8, enable_adjoint=True))
+    sim.init_droplet(10.0, 0.5, 4.0)
+    f = sim.populations(device=True)
+    small = torch.zeros(9 * 8 * 19, dtype=torch.float64, device=f.device)
+    th = torch.zeros((2, 20), dtype=torch.float64, device=f.device)
+    G = torch.zeros(2, dtype=torch.float64, device=f.device)
+    with pytest.raises(AssertionError):
+        sim.adjoint_step(f, small, torch.empty_like(f), th, G)
+    with pytest.raises(AssertionError):
+        sim.adjoint_step(f, f.clone(), torch.empty_like(f), th[:, :10].contiguous(), G)
+    with pytest.raises(AssertionError):
+        sim.set_state(sim.get_state().cpu())
+    sim.close()
