@@ -145,6 +145,7 @@ class LBM:
         xa, xp = _dptr(np.atleast_1d(xc))
         ya, yp = _dptr(np.atleast_1d(yc))
         ra, rp = _dptr(np.atleast_1d(R))
+        assert len(xa) == len(ya) == len(ra), "xc, yc and R need one entry per droplet"
         check(self.lib.lbm_init_droplet(self.ctx, inst, len(xa), xp, yp, rp, float(width), float(rho_l),
                                         float(rho_v)))
 
