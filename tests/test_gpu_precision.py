@@ -200,3 +200,35 @@ def test_c2_measured_angle_settles_near_prescribed(deg):
     print(f"\n  c2 theta={deg}: measured {th:.2f} deg after 100 000 steps")
     assert d["nonfinite"] == 0 and d["ghost_clamps"] == 0
     assert abs(th - deg) <= 3.0, th
+
+
+@pytest.mark.parametrize("ratio", [100, 1000])
+def test_fp32_in_the_papers_setting_tracks_fp64(ratio):
+    """The paper's own model (Table 1 EOS, kappa = 0.5 with Lambda = diag(0,1,...,1): the MRT form) on the 1024 x 512
+    geometry with a 60 deg cap of radius 120, 20 000 steps: FP32 storage shifted by rho_v (FP64 EOS below
+    sqrt(rho_v rho_l)) against FP64 on the GPU. Measured: the angles agree to 0.001 deg (59.83 / 59.59 deg at ratios
+    100 / 1000), FP32 mass drift 2e-8 / 7e-9, density difference 2.3e-5 / 1.9e-5 of rho_l. Checked: angle within
+    0.5 deg, FP32 mass drift within 1e-6, density difference within 2e-4 of rho_l."""
+    import paper_1501_05430_amd as P
+    pw = {100: (0.1633, -0.02, 0.33333, 1.0, 100.0), 1000: (0.2, -0.01, 0.33333, 1.0, 1000.0)}[ratio]
+    case = W.c2_angle(60)
+    out = {}
+    for precision in ("f64", "f32_shifted"):
+        sim = P.LBM(P.make_params(case.nx, case.ny, 1.0, precision=precision, piecewise=pw, kappa=0.5,
+                                  check_every=1000, **P.fp32_options(1.0, precision, piecewise=pw)))
+        sim.apply_wetting(case.theta_bottom, case.theta_top)
+        sim.init_droplet(case.xc, case.yc, case.R)
+        m0 = sim.mass()
+        sim.step(20000)
+        th = math.degrees(sim.measure_contact_angle(BOX, 0)[0])
+        out[precision] = (sim.rho()[1:-1], abs(sim.mass() - m0) / m0, th, sim.diag())
+        sim.close()
+    r64, d64, th64, g64 = out["f64"]
+    r32, d32, th32, g32 = out["f32_shifted"]
+    err = np.abs(r32 - r64).max() / pw[4]
+    print(f"\n  ratio {ratio}: theta FP64 {th64:.3f} / FP32 {th32:.3f}, mass drift FP64 {d64:.1e} / FP32 {d32:.1e}, "
+          f"max|drho|/rho_l {err:.1e}")
+    assert g64["nonfinite"] == 0 and g32["nonfinite"] == 0
+    assert abs(th32 - th64) <= THETA_TOL
+    assert d64 <= MASS64 and d32 <= 1e-6
+    assert err <= 2e-4
