@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -90,7 +92,8 @@ def copy_bandwidth(nbytes=1 << 30, reps=20):
 
 
 def cpu_baseline(case, target_s=15.0, max_steps=400):
-    """The FP64 reference on the same lattice and initial state, timed on the host's cores."""
+    """The FP64 reference on the same lattice and initial state, timed on the host's cores. Also returns its state
+    (steps taken, fluid-row density, liquid density) for the accuracy report."""
     import oracle
     sim = oracle.Sim(case.nx, case.ny, case.T_over_Tc, theta_bottom=case.theta_bottom, theta_top=case.theta_top)
     sim.init_droplets(case.xc, case.yc, case.R)
@@ -100,6 +103,8 @@ def cpu_baseline(case, target_s=15.0, max_steps=400):
         sim.run(5)
         n += 5
     dt = time.perf_counter() - t0
+    rho_ref, _ = sim.density()
+    ref = (n + 2, rho_ref[1:-1].copy(), sim.coexistence()[1])
     return {
         "value": round(case.fluid_nodes * n / dt / 1e6, 3),
         "unit": "MLUPS",
@@ -108,7 +113,22 @@ def cpu_baseline(case, target_s=15.0, max_steps=400):
         "sample": f"{case.nx}x{case.ny} lattice (same initial state), FP64 reference, {n} steps after 2 untimed, "
                   f"{dt:.1f} s",
         "single_core": cpu_baseline_one_core(),
-    }
+    }, ref
+
+
+def error_vs_oracle(case, ref):
+    """The headline configuration (FP32 shifted) and FP64, each stepped on the GPU as far as the CPU reference went
+    from the same initial state: max |rho - rho_ref| / rho_l (FP32) and / max rho_ref (FP64) over the fluid rows."""
+    steps, rho_ref, rho_l = ref
+    out = {"steps": steps}
+    for precision, scale, key in (("f32_shifted", rho_l, "f32_shifted_max_drho_over_rho_l"),
+                                  ("f64", np.abs(rho_ref).max(), "f64_max_drho_rel")):
+        sim = make_sim(case, precision, check_every=100)
+        sim.step(steps)
+        rho = sim.rho()[1:-1]
+        sim.close()
+        out[key] = float(f"{np.abs(rho - rho_ref).max() / scale:.3e}")
+    return out
 
 
 _ONE_CORE = """
@@ -334,7 +354,8 @@ def main():
             out["extras"]["adjoint_fp64_same_lattice"]["mlups"] / out["extras"]["fp64_same_lattice"]["mlups"], 3)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"], ref = cpu_baseline(case)
+        out["error_vs_oracle"] = error_vs_oracle(case, ref)
 
     print(json.dumps(out), flush=True)
 
