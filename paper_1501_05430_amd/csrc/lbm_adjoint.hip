@@ -184,33 +184,29 @@ __device__ inline void collide_mrt_adj(const InstDesc& d, const double (&fl)[9],
   const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
   const double v2 = vx * vx + vy * vy;
   const double sn = d.inv_tau;
-  const double sr[9] = {0.0, d.s_e, d.s_eps, 0.0, d.s_q, 0.0, d.s_q, sn, sn};
-  const double meq[9] = {rho, rho * (-2.0 + 3.0 * v2), rho * (1.0 - 3.0 * v2), rho * vx, -rho * vx, rho * vy,
-                         -rho * vy, rho * (vx * vx - vy * vy), rho * vx * vy};
   double dmb[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
+  for (int k = 1; k < 9; ++k) {
     double a = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) a += kMom[k][i] * ls[i];
     dmb[k] = a / kMomNorm[k];
   }
-  double a[9], b[9], mb[9];
-  double rhob = 0.0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const bool nc = k == 1 || k == 2 || k == 4 || k == 6 || k == 7 || k == 8;
-    mb[k] = nc ? -sr[k] * dmb[k] : 0.0;               // through m_k = (M f)_k
-    a[k] = nc ? sr[k] * dmb[k] : 0.0;                 // adjoint of m_eq,k
-    b[k] = nc ? (1.0 - 0.5 * sr[k]) * dmb[k] : 0.0;   // adjoint of S_k
-    rhob += a[k] * meq[k] / rho;
-  }
-  double vbx = 6.0 * rho * vx * (a[1] - a[2]) - rho * a[4] + 2.0 * rho * vx * a[7] + rho * vy * a[8];
-  double vby = 6.0 * rho * vy * (a[1] - a[2]) - rho * a[6] - 2.0 * rho * vy * a[7] + rho * vx * a[8];
-  vbx += 6.0 * Fx * (b[1] - b[2]) + 2.0 * Fx * b[7] + Fy * b[8];
-  vby += 6.0 * Fy * (b[1] - b[2]) - 2.0 * Fy * b[7] + Fx * b[8];
-  Fbx = dmb[3] + 6.0 * vx * (b[1] - b[2]) - b[4] + 2.0 * vx * b[7] + vy * b[8];
-  Fby = dmb[5] + 6.0 * vy * (b[1] - b[2]) - b[6] - 2.0 * vy * b[7] + vx * b[8];
+  // a_k = s_k dm_bar_k is the adjoint of m_eq,k; the relaxation's term through m = M f is -a_k; the forcing's
+  // adjoint is b_k = (1 - s_k/2) dm_bar_k = dm_bar_k - a_k / 2
+  const double a1 = d.s_e * dmb[1], a2 = d.s_eps * dmb[2], a4 = d.s_q * dmb[4], a6 = d.s_q * dmb[6];
+  const double a7 = sn * dmb[7], a8 = sn * dmb[8];
+  const double b12 = (dmb[1] - 0.5 * a1) - (dmb[2] - 0.5 * a2), b4 = dmb[4] - 0.5 * a4, b6 = dmb[6] - 0.5 * a6;
+  const double b7 = dmb[7] - 0.5 * a7, b8 = dmb[8] - 0.5 * a8;
+  // m_eq / rho: (-2 + 3 v^2, 1 - 3 v^2, -v_x, -v_y, v_x^2 - v_y^2, v_x v_y) on e, eps, q_x, q_y, p_xx, p_xy
+  double rhob = a1 * (-2.0 + 3.0 * v2) + a2 * (1.0 - 3.0 * v2) - a4 * vx - a6 * vy + a7 * (vx * vx - vy * vy) +
+                a8 * vx * vy;
+  double vbx = 6.0 * rho * vx * (a1 - a2) - rho * a4 + 2.0 * rho * vx * a7 + rho * vy * a8;
+  double vby = 6.0 * rho * vy * (a1 - a2) - rho * a6 - 2.0 * rho * vy * a7 + rho * vx * a8;
+  vbx += 6.0 * Fx * b12 + 2.0 * Fx * b7 + Fy * b8;
+  vby += 6.0 * Fy * b12 - 2.0 * Fy * b7 + Fx * b8;
+  Fbx = dmb[3] + 6.0 * vx * b12 - b4 + 2.0 * vx * b7 + vy * b8;
+  Fby = dmb[5] + 6.0 * vy * b12 - b6 - 2.0 * vy * b7 + vx * b8;
   qb[0] = 1.5 * d.s_e * dmb[1] - sn * dmb[7];
   qb[1] = 1.5 * d.s_e * dmb[1] + sn * dmb[7];
   qb[2] = -sn * dmb[8];
@@ -219,11 +215,12 @@ __device__ inline void collide_mrt_adj(const InstDesc& d, const double (&fl)[9],
   Fbx += 0.5 * vbx / rho;
   Fby += 0.5 * vby / rho;
   rhob -= (vbx * vx + vby * vy) / rho;
+  const double mr[9] = {0.0, -a1, -a2, 0.0, -a4, 0.0, -a6, -a7, -a8};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     double m = 0.0;
 #pragma unroll
-    for (int k = 1; k < 9; ++k) m += kMom[k][i] * mb[k];
+    for (int k = 1; k < 9; ++k) m += kMom[k][i] * mr[k];
     lam[i] = ls[i] + m + rhob + jbx * kEX[i] + jby * kEY[i];
   }
 }
@@ -345,7 +342,7 @@ __device__ inline void force_vals(const InstDesc& d, double pmL, double pm, doub
 // Eq. 14 on the boundary rows; without it only the BGK collision with geometric walls is compiled.
 // T: storage type of the state and of lambda (double, or float for lbm_adjoint_step_f32); the arithmetic is FP64.
 template <bool EXT, class T>
-__global__ __launch_bounds__(FL, EXT ? 1 : 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
+__global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ descs, int inst,
                                                   const T* __restrict__ f, const T* __restrict__ lam1,
                                                   T* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
                                                   int ntasks) {
