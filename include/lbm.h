@@ -9,6 +9,9 @@
  *   -> interaction force, hybrid form with parameter A            (Eq. 9, weights of Eq. 7)
  *   -> BGK collision with Guo forcing, v = (j + F/2)/rho          (Eq. 1-6 with diag(0,1,...,1), Sec. 3.1)
  *   -> streaming with halfway bounce-back at the walls.
+ * Per instance (lbm_params) the EOS may instead be the piecewise-linear one of Eq. 11-13, the collision the MRT
+ * form of Eq. 15 with general rates and the surface-tension source of Eq. 16-17, and the walls those of the
+ * comparison method (the fluid-solid force of Eq. 14) or none (periodic rows).
  *
  * Lattice: D2Q9, velocities e0=(0,0), e1..e4=(1,0),(0,1),(-1,0),(0,-1), e5..e8=(1,1),(-1,1),(-1,-1),(1,-1)
  * (the moment order of Eq. 4). Grid nx x ny with x periodic; rows 0 and ny-1 are the ghost layer beside the
@@ -132,6 +135,8 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n_inst);
 int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws_bytes, void* hip_stream,
                lbm_ctx** out);
 
+/* Free the context (host memory only; the workspace and the stream stay the caller's). NULL: LBM_E_INVALID. Work
+ * already queued on the stream is not waited for: synchronize the stream before reusing the workspace. */
 int lbm_destroy(lbm_ctx* c);
 
 /* Host FP64 EOS data of instance inst. Carnahan-Starling: out[0] = rho_v, out[1] = rho_l (Maxwell equal-area
