@@ -99,11 +99,12 @@ def test_calls_out_of_order_are_errors():
     sim.close()
 
 
-def test_adjoint_at_the_largest_lattice():
-    """16384 columns x 14563 fluid rows in FP64 (9 * nx * rows just below 2^31, about 95 GB of device memory): two
-    exact properties of the reverse step at every node. The step conserves mass, so the cotangent lambda = 1 (the
-    derivative of the total mass) comes back as lambda = 1 with no angle or G gradient; and the reverse step is
-    linear, so doubling lambda doubles every output bit for bit."""
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_at_the_largest_lattice(storage):
+    """16384 columns x 14563 fluid rows (9 * nx * rows just below 2^31; up to about 130 GB of device memory), both
+    storage forms of the reverse step, two exact properties at every node. The step conserves mass, so the
+    cotangent lambda = 1 (the derivative of the total mass) comes back as lambda = 1 with no angle or G gradient;
+    and the reverse step is linear, so doubling lambda doubles every output bit for bit."""
     import torch
     import paper_1501_05430_amd as P
     nx = 16384
@@ -113,6 +114,8 @@ def test_adjoint_at_the_largest_lattice():
     sim.init_droplet([nx / 2, 3000.0], [0.5 - 3000 * math.cos(math.radians(60.0)), 9000.0], [3000.0, 1500.0])
     sim.step(5)
     f = sim.populations(device=True)
+    if storage == "f32":   # lbm_adjoint_step_f32: the same indexing over FP32 arrays
+        f = f.float()
     lam1 = torch.ones_like(f)
     lam0 = torch.empty_like(f)
     thb = torch.zeros((2, nx), dtype=torch.float64, device=f.device)
@@ -124,7 +127,7 @@ def test_adjoint_at_the_largest_lattice():
     assert float(thb.abs().max()) <= 1e-9 and float(Gb.abs().max()) <= 1e-6 * nx * nyf * 1e-6, (thb.abs().max(), Gb)
     g = torch.Generator(device=f.device)
     g.manual_seed(7)
-    torch.randn(lam1.shape, generator=g, device=f.device, dtype=torch.float64, out=lam1)
+    torch.randn(lam1.shape, generator=g, device=f.device, dtype=lam1.dtype, out=lam1)
     sim.adjoint_step(f, lam1, lam0, thb.zero_(), Gb.zero_())
     first = (lam0.clone(), thb.clone(), Gb.clone())
     lam1.mul_(2.0)
