@@ -4,7 +4,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.cpp")
-LIB = os.path.join(HERE, "liblbm_oracle.so")
+# LBM_ORACLE_LIB points the loader at another build of the reference (the mutation tests load planted copies)
+LIB = os.environ.get("LBM_ORACLE_LIB") or os.path.join(HERE, "liblbm_oracle.so")
 
 
 def build(force: bool = True) -> str:

@@ -657,6 +657,24 @@ int ora_force(const ora_params* p, const double* f, const double* theta_bot, con
   return 0;
 }
 
+// The interaction force of Eq. (9) (Martys-Chen wall term of Eq. 14 included when wall_mode = 1, no body force) on
+// a given psi field [ny][nx] (every row read as given, the ghost rows too), at every fluid node; other rows are
+// left at zero. It evaluates Oracle::force, the step's own force, on psi values chosen by the caller.
+int ora_force_psi(const ora_params* p, const double* psi, double* Fx, double* Fy) {
+  if (!params_ok(p)) return 1;
+  Oracle<double> o(*p, p->G, p->G);
+  std::memcpy(o.psi.data(), psi, sizeof(double) * o.psi.size());
+  for (int y = 0; y < p->ny; ++y) {
+    for (int x = 0; x < p->nx; ++x) {
+      size_t k = (size_t)y * p->nx + x;
+      Fx[k] = 0.0;
+      Fy[k] = 0.0;
+      if (o.fluid_row(y)) o.force(x, y, &Fx[k], &Fy[k]);
+    }
+  }
+  return 0;
+}
+
 // One BGK-Guo collision of a single node (no streaming); f_in[9] -> f_out[9], given the total force.
 int ora_collide_node(const ora_params* p, const double* f_in, double Fx, double Fy, double* f_out) {
   if (!params_ok(p)) return 1;

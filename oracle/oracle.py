@@ -48,6 +48,7 @@ def lib():
         L.ora_run_cplx.argtypes = [pp, p, i64, p, p, p, p]; L.ora_run_cplx.restype = C.c_int
         L.ora_density.argtypes = [pp, p, p, p, p, p]; L.ora_density.restype = C.c_int
         L.ora_force.argtypes = [pp, p, p, p, p, p]; L.ora_force.restype = C.c_int
+        L.ora_force_psi.argtypes = [pp, p, p, p]; L.ora_force_psi.restype = C.c_int
         L.ora_collide_node.argtypes = [pp, p, d, d, p]; L.ora_collide_node.restype = C.c_int
         L.ora_ghost_density.argtypes = [d, d, d, d, d, i32]; L.ora_ghost_density.restype = d
         L.ora_psi.argtypes = [pp, d]; L.ora_psi.restype = d
@@ -250,6 +251,18 @@ def qtensor(sim, psi):
     return q
 
 
+def force_psi(sim, psi):
+    """The interaction force of Eq. (9) (no body force) on a given psi field [ny, nx]: (Fx, Fy), [ny, nx] each,
+    zero outside the fluid rows."""
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    assert psi.shape == (sim.ny, sim.nx)
+    Fx = np.zeros_like(psi)
+    Fy = np.zeros_like(psi)
+    if lib().ora_force_psi(C.byref(sim.p), _ptr(psi), _ptr(Fx), _ptr(Fy)):
+        raise ValueError("bad parameters")
+    return Fx, Fy
+
+
 def collide_node(sim, f_in, Fx, Fy):
     f_in = np.ascontiguousarray(f_in, np.float64)
     out = np.zeros(9)
@@ -268,4 +281,4 @@ def psi(sim, rho):
 
 __all__ = ["OraParams", "lib", "cs_pressure", "cs_dpdrho", "cs_d2pdrho2", "cs_mu", "cs_critical", "cs_maxwell",
            "cs_rho_cap", "pw_breakpoints", "pw_pressure", "pw_rho_cap", "ghost_density", "Sim", "collide_node",
-           "collide_mrt_node", "qtensor", "psi", "num_threads"]
+           "collide_mrt_node", "qtensor", "psi", "force_psi", "num_threads"]
