@@ -29,6 +29,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
               for n in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_c3.json")
+TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step_f32_batched_c4.json")
 
 
 def kernel_sha():
@@ -38,6 +39,17 @@ def kernel_sha():
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def profile_traffic(path):
+    """HBM bytes per launch from a committed counter summary, if it was taken on the current step sources."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("kernel_source_sha256") != kernel_sha():
+        return None
+    return tr.get("hbm_bytes_per_launch")
 
 
 def make_sim(case, precision, check_every=100, **kw):
@@ -51,44 +63,72 @@ def make_sim(case, precision, check_every=100, **kw):
 
 
 def timed_steps(sim, nsteps, inst=0):
-    """HIP-event time (ms) of nsteps steps on the library's stream; returns (ms, stable)."""
-    import torch
+    """Device time (ms) of nsteps steps: HIP events that the library records on its own stream right before the
+    first queued launch and after the last one (graph replays, device checks included; the closing host
+    synchronization excluded). Returns (ms, stable)."""
     import paper_1501_05430_amd as P
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(sim.stream)
-    stable = True
     try:
-        sim.step(nsteps, inst=inst)
+        return sim.step_timed(nsteps, inst=inst), True
     except P.LbmError as e:
         if e.code != 4:
             raise
-        stable = False
-    e1.record(sim.stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1), stable
+        return float("nan"), False
 
 
-def copy_bandwidth(nbytes=1 << 30, reps=20):
-    """Achievable device-copy bandwidth on this GPU (torch copy of nbytes, read + write counted)."""
+def _probe_lib():
+    import ctypes as C
+    from paper_1501_05430_amd import _build
+    lib = C.CDLL(_build.PROBE_LIB)
+    lib.bwp_copy.restype = C.c_int
+    lib.bwp_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    lib.bwp_pattern.restype = C.c_int
+    lib.bwp_pattern.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
+    return lib
+
+
+def bandwidth_ceilings(nx, ny, strip_rows=32, reps=50):
+    """What plain memory movement achieves on this GPU, with two buffers of the FP32 step's state size
+    (9 x (ny-2) x pitch floats each), ping-pong as the step uses them: a float4 and a float streaming copy (read +
+    write bytes), and the step's own access pattern without arithmetic (bw_probe.hip; 72 B per fluid node)."""
     import torch
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
+    lib = _probe_lib()
+    pitch = (nx + 63) // 64 * 64
+    n = 9 * (ny - 2) * pitch
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    s = torch.cuda.current_stream()
+    sp = s.cuda_stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(launch):
+        for k in range(4):
+            launch(k)
+        e0.record(s)
+        for k in range(reps):
+            launch(k)
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    for vec in (4, 1):
+        def cp(k, vec=vec):
+            src, dst = (a, b) if k % 2 == 0 else (b, a)
+            assert lib.bwp_copy(src.data_ptr(), dst.data_ptr(), 4 * n, vec, sp) == 0
+        ms = timed(cp)
+        out[f"copy_float{vec if vec > 1 else ''}_gbs"] = round(2 * 4 * n / ms / 1e6, 1)
+
+    def pat(k):
+        src, dst = (a, b) if k % 2 == 0 else (b, a)
+        assert lib.bwp_pattern(src.data_ptr(), dst.data_ptr(), nx, ny, pitch, strip_rows, k % 2, sp) == 0
+    ms = timed(pat)
+    out["step_pattern_us"] = round(ms * 1e3, 2)
+    out["step_pattern_gbs_alg"] = round(72 * nx * (ny - 2) / ms / 1e6, 1)
+    out["buffer_bytes"] = 4 * n
     del a, b
     torch.cuda.empty_cache()
-    return round(2 * nbytes / ms / 1e6, 1)
+    return out
 
 
 def cpu_baseline(case, target_s=15.0, max_steps=400):
@@ -200,12 +240,17 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
         s.close()
     mlups_b = nodes * steps_batched / ms_b / 1e3
     mlups_p = nodes * steps_plain / dt_plain / 1e6
+    ach = 72 * nodes * steps_batched / ms_b / 1e6
+    traffic = profile_traffic(TRAFFIC_FILE_C4)
     return {
         "instances": len(cases), "fluid_nodes": nodes, "dtype": "f32", "precision": "f32_shifted",
         "batched_mlups": round(mlups_b, 1), "batched_stable": stable_b,
         "batched_gbs_alg": round(72 * nodes * steps_batched / ms_b / 1e6, 1),
         "plain_sequential_mlups": round(mlups_p, 1),
         "speedup": round(mlups_b / mlups_p, 2),
+        # the batched launch (one step of all instances) against the HBM peak: 72 B per fluid node
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic},
     }
 
 
@@ -283,7 +328,7 @@ def main():
     P.load()
 
     case = W.c3_large()
-    copy_gbs = copy_bandwidth()
+    ceilings = bandwidth_ceilings(case.nx, case.ny)
     sim = make_sim(case, "f32_shifted", check_every=100)
     if args.autotune:
         sim.autotune(trial_steps=10)
@@ -298,12 +343,7 @@ def main():
     bytes_alg = 72 * nodes  # 9 FP32 populations read + 9 written per fluid node and step
     achieved = bytes_alg / (ms_step * 1e-3) / 1e9
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha256") == kernel_sha():
-            traffic = tr.get("hbm_bytes_per_launch")
+    traffic = profile_traffic(TRAFFIC_FILE)
 
     out = {
         "metric": "MLUPS & % HBM roofline; FP32/batched/adjoint vs plain FP64 at stated error",
@@ -329,7 +369,10 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # HBM bytes of the counters (when current) over this run's time per step
             "traffic_gbs": round(traffic / (ms_step * 1e-3) / 1e9, 1) if traffic else None,
-            "copy_gbs_on_this_gpu": copy_gbs,
+            # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
+            # and the step's access pattern without arithmetic
+            "copy_gbs_on_this_gpu": ceilings["copy_float4_gbs"],
+            "ceilings": ceilings,
         },
     }
 

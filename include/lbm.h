@@ -145,6 +145,12 @@ int lbm_destroy(lbm_ctx* c);
  * density with real psi (Eq. 10), or 1e300 where psi is real at every density above the vapour. */
 int lbm_eos_info(const lbm_ctx* c, int32_t inst, double out[6]);
 
+/* Coexistence densities of instance inst (host FP64, solved at lbm_create): out[0] = rho_v, out[1] = rho_l. For
+ * Carnahan-Starling the Maxwell equal-area pair at T_over_Tc T_c (the counterpart of the two-phase conditions the
+ * paper writes for Eq. 11 as Eq. 12-13); for the piecewise-linear EOS the pair pw_rho that Eq. 12-13 were solved
+ * for. lbm_eos_info reports these with the rest of the EOS data. */
+int lbm_coexistence(const lbm_ctx* c, int32_t inst, double out[2]);
+
 /* Initial state (droplets at rest): rho(x, y) = rho_v + (rho_l - rho_v) (1 - tanh(2 (r - R_k)/width)) / 2,
  * the maximum over the n droplets, r the distance from node (x, y) to (xc[k], yc[k]) with the nearest periodic
  * image in x; f_i = w_i rho. rho_l <= 0 or rho_v <= 0 selects the Maxwell value. The setup of Sec. 3.1 is one
@@ -163,6 +169,11 @@ int lbm_apply_wetting(lbm_ctx* c, int32_t inst, const double* theta_bottom, cons
  * With check_every > 0 a device check runs every check_every steps and after the last step; the call then
  * synchronizes the stream once at its end and returns LBM_E_UNSTABLE if a check saw a non-finite density. */
 int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps);
+
+/* lbm_step with device timing: HIP events on the context's stream bracket the queued steps (recorded before the
+ * first launch and after the last, ahead of the closing synchronization of the checks), and *ms receives the
+ * elapsed time between them. Synchronizes the stream. Same status as lbm_step (LBM_E_UNSTABLE still sets *ms). */
+int lbm_step_timed(lbm_ctx* c, int32_t inst, int64_t nsteps, double* ms);
 
 /* Contact angle of the droplet inside box = {x_lo, x_hi, y_lo, y_hi} (half-open node ranges; rows are clipped
  * to the fluid rows) on wall 0 (bottom) or 1 (top). Reading of the method (the paper quotes angles without the
@@ -222,6 +233,16 @@ int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const do
  * as above. Same preconditions and errors as lbm_adjoint_step. */
 int lbm_adjoint_step_f32(lbm_ctx* c, int32_t inst, const float* d_state_n, const float* d_lambda_np1,
                          float* d_lambda_n, double* d_theta_bar, double* d_G_bar);
+
+/* Adjoint of the density readout rho = sum_i f_i (the fluid rows of lbm_get_rho, Eq. 1's zeroth moment): given
+ * d_grad_rho = dL/drho_N [ny-2][nx] (FP64, device), writes lambda_N = dL/df_N [9][ny-2][nx] (every population of a
+ * node receives that node's dL/drho; FP64, or FP32 for the _f32 form that lbm_adjoint_step_f32 takes) and sets the
+ * accumulators d_theta_bar [2][nx] and d_G_bar [2] to zero: the start of a reverse sweep of lbm_adjoint_step calls.
+ * Stream-ordered; needs no enable_adjoint. */
+int lbm_adjoint_seed_rho(lbm_ctx* c, int32_t inst, const double* d_grad_rho, double* d_lambda, double* d_theta_bar,
+                         double* d_G_bar);
+int lbm_adjoint_seed_rho_f32(lbm_ctx* c, int32_t inst, const double* d_grad_rho, float* d_lambda,
+                             double* d_theta_bar, double* d_G_bar);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);

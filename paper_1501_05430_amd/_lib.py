@@ -64,6 +64,11 @@ _SIGS = {
                                    C.c_void_p]),
     "lbm_adjoint_step_f32": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p]),
+    "lbm_coexistence": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "lbm_step_timed": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)]),
+    "lbm_adjoint_seed_rho": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_adjoint_seed_rho_f32": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p]),
     "lbm_last_error": (C.c_char_p, []),
 }
 

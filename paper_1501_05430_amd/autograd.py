@@ -7,9 +7,12 @@ segment is recomputed (its states kept on the device) before its adjoint steps r
 storage the segment's states and the adjoints are kept in FP32 and go through lbm_adjoint_step_f32 (FP64
 arithmetic, lambda rounded to FP32 once per step), unless fp32_adjoint=False asks for the FP64 entry point.
 
-G enters the model twice (the force prefactor of Eq. 9 and the G inside the psi inversion of Eq. 10); the
-gradient returned for G is their sum, the total derivative, which is zero for this model. The two parts of the
-last backward are kept in `Rollout.last_G_parts` = (dL/dG_f, dL/dG_psi).
+G enters the model twice (the force prefactor of Eq. 9, and of Q in Eq. 17, and the G inside the psi inversion of
+Eq. 10); the library returns the two partials and, since one G feeds both, the gradient returned for G is their
+sum (the chain rule of that tie). With geometric walls (or periodic rows) that total is zero: every term depends on
+G only through G psi^2, which Eq. 10 fixes. With Martys-Chen walls it is not: the fluid-solid force of Eq. 14 has
+its own G_w and scales with psi alone, so it changes with G. The two parts of the last backward are kept in
+`Rollout.last_G_parts` = (dL/dG_f, dL/dG_psi).
 """
 import numpy as np
 import torch
@@ -48,10 +51,12 @@ class Rollout(torch.autograd.Function):
         dev = sim.device
         dtype = torch.float32 if ctx.f32 else torch.float64
         with torch.cuda.stream(sim.stream):
-            lam = grad_rho.detach().to(dev, dtype).contiguous().unsqueeze(0).expand(9, -1, -1).contiguous()
+            g = grad_rho.detach().to(dev, torch.float64).contiguous()
+            lam = torch.empty((9, p.ny - 2, p.nx), dtype=dtype, device=dev)
             lam_prev = torch.empty_like(lam)
-            theta_bar = torch.zeros((2, p.nx), dtype=torch.float64, device=dev)
-            G_bar = torch.zeros(2, dtype=torch.float64, device=dev)
+            theta_bar = torch.empty((2, p.nx), dtype=torch.float64, device=dev)
+            G_bar = torch.empty(2, dtype=torch.float64, device=dev)
+        sim.adjoint_seed_rho(g, lam, theta_bar, G_bar)  # lambda_N = dL/drho_N on every population; sums zeroed
         sim.apply_wetting(*ctx.theta)
         starts = list(range(0, nsteps, seg))
         for si in reversed(range(len(starts))):

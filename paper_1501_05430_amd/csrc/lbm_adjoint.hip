@@ -658,7 +658,37 @@ hipError_t launch_adjoint_t(const InstDesc* d_desc, const InstDesc& h, int inst,
   return hipGetLastError();
 }
 
+// Adjoint of the density readout rho = sum_i f_i of the streamed populations (fluid rows): every population of a
+// node receives that node's dL/drho, lambda_i(x) = grad_rho(x). The accumulators theta_bar [2][nx] and G_bar [2]
+// start at zero.
+template <class T>
+__global__ __launch_bounds__(AB) void ka_seed_rho(const double* __restrict__ grad_rho, T* __restrict__ lam,
+                                                  double* __restrict__ theta_bar, double* __restrict__ G_bar,
+                                                  int64_t nodes, int nx) {
+  const int64_t k = (int64_t)blockIdx.x * AB + threadIdx.x;
+  if (k < nodes) {
+    const T g = (T)grad_rho[k];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lam[i * nodes + k] = g;
+  }
+  if (k < 2 * (int64_t)nx) theta_bar[k] = 0.0;
+  if (k < 2) G_bar[k] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_adjoint_seed_rho(bool f32, const double* grad_rho, void* lam, double* theta_bar, double* G_bar,
+                                   int nx, int nyf, hipStream_t s) {
+  const int64_t nodes = (int64_t)nx * nyf;
+  const int64_t work = std::max<int64_t>(nodes, 2 * (int64_t)nx);
+  const dim3 grid((unsigned)((work + AB - 1) / AB));
+  if (f32)
+    hipLaunchKernelGGL(ka_seed_rho<float>, grid, dim3(AB), 0, s, grad_rho, (float*)lam, theta_bar, G_bar, nodes, nx);
+  else
+    hipLaunchKernelGGL(ka_seed_rho<double>, grid, dim3(AB), 0, s, grad_rho, (double*)lam, theta_bar, G_bar, nodes,
+                       nx);
+  return hipGetLastError();
+}
 
 hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc, bool f32,
                           const void* f_n, const void* lam_np1, void* lam_n, double* theta_bar, double* G_bar,

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -351,6 +352,69 @@ Layout make_layout(const lbm_params* p, int32_t n) {
 
 }  // namespace
 
+namespace lbm {
+
+int report_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int measure_contact_angle_field(const double* d_rho, int nx, int ny, int wall, const int32_t b[4], double* d_partials,
+                                hipStream_t s, double out[5]) {
+  // host copies of the partials live on the stack: the measurement allocates nothing
+  double part[kMeasurePartials];
+  HIP_TRY(launch_minmax(d_rho, nx, ny, b, d_partials, kMeasureBlocks, s));
+  HIP_TRY(hipMemcpyAsync(part, d_partials, sizeof(double) * 2 * kMeasureBlocks, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double lo = part[0], hi = part[kMeasureBlocks];
+  for (int k = 0; k < kMeasureBlocks; ++k) {
+    lo = std::min(lo, part[k]);
+    hi = std::max(hi, part[kMeasureBlocks + k]);
+  }
+  const double mid = 0.5 * (hi + lo);
+  const double sx = 0.5 * (b[0] + b[1]), sy = 0.5 * (b[2] + b[3]);
+  HIP_TRY(launch_ca_moments(d_rho, nx, ny, b, wall, mid, sx, sy, d_partials, kMeasureBlocks, s));
+  HIP_TRY(hipMemcpyAsync(part, d_partials, sizeof(double) * kMeasurePartials, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double m[kMeasureMoments] = {0};
+  for (int j = 0; j < kMeasureMoments; ++j)
+    for (int k = 0; k < kMeasureBlocks; ++k) m[j] += part[j * kMeasureBlocks + k];
+  if (m[0] < 3) return fail(LBM_E_INVALID, "too few interface points in the box (%g)", m[0]);
+  // Kasa normal equations for x^2 + y^2 + D x + E y + F = 0.
+  double M3[3][4] = {{m[3], m[5], m[1], -(m[6] + m[7])},
+                     {m[5], m[4], m[2], -(m[8] + m[9])},
+                     {m[1], m[2], m[0], -(m[3] + m[4])}};
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (std::fabs(M3[r][col]) > std::fabs(M3[piv][col])) piv = r;
+    if (M3[piv][col] == 0.0) return fail(LBM_E_INVALID, "degenerate circle fit");
+    if (piv != col)
+      for (int k = 0; k < 4; ++k) std::swap(M3[piv][k], M3[col][k]);
+    for (int r = col + 1; r < 3; ++r) {
+      const double f = M3[r][col] / M3[col][col];
+      for (int k = col; k < 4; ++k) M3[r][k] -= f * M3[col][k];
+    }
+  }
+  double sol[3];
+  for (int r = 2; r >= 0; --r) {
+    double v = M3[r][3];
+    for (int k = r + 1; k < 3; ++k) v -= M3[r][k] * sol[k];
+    sol[r] = v / M3[r][r];
+  }
+  const double xc = -0.5 * sol[0], yc = -0.5 * sol[1];
+  const double R = std::sqrt(xc * xc + yc * yc - sol[2]);
+  const double Xc = xc + sx, Yc = yc + sy;
+  const double yw = wall == 0 ? 0.5 : ny - 1.5;
+  double cth = wall == 0 ? (yw - Yc) / R : (Yc - yw) / R;
+  cth = std::max(-1.0, std::min(1.0, cth));
+  out[0] = std::acos(cth);
+  out[1] = R;
+  out[2] = Xc;
+  out[3] = Yc;
+  out[4] = m[0];
+  return LBM_OK;
+}
+
+}  // namespace lbm
+
 struct lbm_ctx {
   std::vector<Inst> inst;
   Layout L;
@@ -363,7 +427,8 @@ struct lbm_ctx {
   std::vector<InstDesc> hdesc;
   std::vector<int32_t> first;       // [n+1] task ranges per instance
   std::vector<WaveTask> tasks;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (selection, length) -> executable graph
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (selection, length, final check) -> graph
+  hipEvent_t ev[2] = {nullptr, nullptr};  // lbm_step_timed: around the queued steps
 
   InstDesc* d_desc() { return (InstDesc*)(ws + L.desc); }
   WaveTask* d_tasks() { return (WaveTask*)(ws + L.tasks); }
@@ -592,6 +657,8 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
 int lbm_destroy(lbm_ctx* c) {
   if (!c) return fail(LBM_E_INVALID, "NULL context");
   c->drop_graphs();
+  for (hipEvent_t& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return LBM_OK;
 }
@@ -614,6 +681,15 @@ int lbm_eos_info(const lbm_ctx* c, int32_t inst, double out[6]) {
   out[3] = pw ? I.pw_r2 : I.T_c;
   out[4] = pw ? 0.0 : I.rho_c;
   out[5] = I.rho_cap;
+  return LBM_OK;
+}
+
+int lbm_coexistence(const lbm_ctx* c, int32_t inst, double out[2]) {
+  if (!c) return fail(LBM_E_INVALID, "NULL context");
+  if (inst < 0 || inst >= (int)c->inst.size()) return fail(LBM_E_INVALID, "instance out of range");
+  if (!out) return fail(LBM_E_INVALID, "out is NULL");
+  out[0] = c->inst[inst].rho_v;
+  out[1] = c->inst[inst].rho_l;
   return LBM_OK;
 }
 
@@ -699,16 +775,24 @@ int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check) {
   return LBM_OK;
 }
 
-int get_graph(lbm_ctx* c, int sel, int len, int K, hipGraphExec_t* out) {
-  auto key = std::make_pair(sel, len);
+// Cached graphs: one per (selection, length, final check); lengths other than the chunk length come from the
+// remainder of a call, so a bounded number of them is kept.
+constexpr size_t kMaxGraphs = 64;
+
+int get_graph(lbm_ctx* c, int sel, int len, int K, bool final_check, hipGraphExec_t* out) {
+  auto key = std::make_tuple(sel, len, final_check ? 1 : 0);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     *out = it->second;
     return LBM_OK;
   }
+  if (c->graphs.size() >= kMaxGraphs) {
+    *out = nullptr;  // the caller queues plain launches
+    return LBM_OK;
+  }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  int rc = queue_steps(c, sel, len, K, false);
+  int rc = queue_steps(c, sel, len, K, final_check);
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (rc != LBM_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -726,41 +810,60 @@ int get_graph(lbm_ctx* c, int sel, int len, int K, hipGraphExec_t* out) {
 
 }  // namespace
 
-int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps) {
+namespace {
+
+// lbm_step; with ev (two events) the first is recorded before the first queued launch and the second after the
+// last one, ahead of the closing host synchronization.
+int step_impl(lbm_ctx* c, int32_t inst, int64_t nsteps, hipEvent_t* ev) {
   if (!c) return fail(LBM_E_INVALID, "NULL context");
   if (inst < -1 || inst >= c->n()) return fail(LBM_E_INVALID, "instance %d out of range", inst);
   if (nsteps < 0) return fail(LBM_E_INVALID, "nsteps < 0");
   for (int i = 0; i < c->n(); ++i)
     if ((inst < 0 || i == inst) && !c->inst[i].initialized)
       return fail(LBM_E_STATE, "instance %d has no state (call lbm_init_droplet or lbm_set_populations)", i);
-  if (nsteps == 0) return LBM_OK;
+  if (ev) HIP_TRY(hipEventRecord(ev[0], c->stream));
+  if (nsteps > 0) {
+    const int K = c->inst[inst < 0 ? 0 : inst].p.check_every;
+    const int len = K > 0 ? (K % 2 == 0 ? K : 2 * K) : 64;
+    int64_t left = nsteps;
+    const bool graphs = c->stream != nullptr && len <= 4096;
+    if (graphs && nsteps >= len) {
+      hipGraphExec_t ex;
+      int rc = get_graph(c, inst, len, K, false, &ex);
+      if (rc != LBM_OK) return rc;
+      while (ex && left >= len) {
+        HIP_TRY(hipGraphLaunch(ex, c->stream));
+        left -= len;
+      }
+    }
+    // The rest (fewer steps than a chunk; graph replays cover a multiple of 2 K steps, so flips restart at 0 and
+    // check positions stay aligned): one graph of exactly that length, or plain launches once the cache is full.
+    if (left > 0 && graphs && left < len) {
+      hipGraphExec_t ex;
+      int rc = get_graph(c, inst, (int)left, K, K > 0, &ex);
+      if (rc != LBM_OK) return rc;
+      if (ex) {
+        HIP_TRY(hipGraphLaunch(ex, c->stream));
+        left = 0;
+      }
+    }
+    if (left > 0) {
+      int rc = queue_steps(c, inst, left, K, K > 0);
+      if (rc != LBM_OK) return rc;
+    }
+    if (nsteps & 1) {
+      for (int i = 0; i < c->n(); ++i) {
+        if (inst >= 0 && i != inst) continue;
+        c->hdesc[i].cur ^= 1;
+        HIP_TRY(launch_set_cur(c->d_desc(), i, c->hdesc[i].cur, c->stream));
+      }
+    }
+    for (int i = 0; i < c->n(); ++i)
+      if (inst < 0 || i == inst) c->inst[i].steps += nsteps;
+  }
+  if (ev) HIP_TRY(hipEventRecord(ev[1], c->stream));
   const int K = c->inst[inst < 0 ? 0 : inst].p.check_every;
-  const int len = K > 0 ? (K % 2 == 0 ? K : 2 * K) : 64;
-  int64_t left = nsteps;
-  if (c->stream != nullptr && nsteps >= len && len <= 4096) {
-    hipGraphExec_t ex;
-    int rc = get_graph(c, inst, len, K, &ex);
-    if (rc != LBM_OK) return rc;
-    while (left >= len) {
-      HIP_TRY(hipGraphLaunch(ex, c->stream));
-      left -= len;
-    }
-  }
-  if (left > 0) {
-    // graph replays cover a multiple of 2 K steps, so flips restart at 0 and check positions stay aligned
-    int rc = queue_steps(c, inst, left, K, K > 0);
-    if (rc != LBM_OK) return rc;
-  }
-  if (nsteps & 1) {
-    for (int i = 0; i < c->n(); ++i) {
-      if (inst >= 0 && i != inst) continue;
-      c->hdesc[i].cur ^= 1;
-      HIP_TRY(launch_set_cur(c->d_desc(), i, c->hdesc[i].cur, c->stream));
-    }
-  }
-  for (int i = 0; i < c->n(); ++i)
-    if (inst < 0 || i == inst) c->inst[i].steps += nsteps;
-  if (K > 0) {
+  if (K > 0 && nsteps > 0) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     std::vector<InstDiag> g(c->n());
     HIP_TRY(hipMemcpy(g.data(), c->d_idiag(), sizeof(InstDiag) * c->n(), hipMemcpyDeviceToHost));
@@ -770,6 +873,23 @@ int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps) {
                     (long long)g[i].nonfinite);
   }
   return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps) { return step_impl(c, inst, nsteps, nullptr); }
+
+int lbm_step_timed(lbm_ctx* c, int32_t inst, int64_t nsteps, double* ms) {
+  if (!c || !ms) return fail(LBM_E_INVALID, "NULL context or ms");
+  for (hipEvent_t& e : c->ev)
+    if (!e) HIP_TRY(hipEventCreate(&e));
+  const int rc = step_impl(c, inst, nsteps, c->ev);
+  if (rc != LBM_OK && rc != LBM_E_UNSTABLE) return rc;
+  HIP_TRY(hipEventSynchronize(c->ev[1]));
+  float t = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
+  *ms = t;
+  return rc;
 }
 
 int lbm_get_diag(lbm_ctx* c, int32_t inst, lbm_diag* out) {
@@ -901,60 +1021,7 @@ int lbm_measure_contact_angle(lbm_ctx* c, int32_t inst, int32_t wall, const int3
   double* rho = c->d_rho_scratch();
   HIP_TRY(launch_wetting(c->storage, c->d_desc(), inst, I.p.nx, c->stream));
   HIP_TRY(launch_get_rho(c->storage, c->d_desc(), inst, I.p.nx, I.p.ny, rho, c->stream));
-  HIP_TRY(launch_minmax(rho, I.p.nx, I.p.ny, b, c->d_partials(), kMeasureBlocks, c->stream));
-  std::vector<double> part(kMeasureBlocks * kMeasureMoments);
-  HIP_TRY(hipMemcpyAsync(part.data(), c->d_partials(), sizeof(double) * 2 * kMeasureBlocks, hipMemcpyDeviceToHost,
-                         c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  double lo = part[0], hi = part[kMeasureBlocks];
-  for (int k = 0; k < kMeasureBlocks; ++k) {
-    lo = std::min(lo, part[k]);
-    hi = std::max(hi, part[kMeasureBlocks + k]);
-  }
-  const double mid = 0.5 * (hi + lo);
-  const double sx = 0.5 * (b[0] + b[1]), sy = 0.5 * (b[2] + b[3]);
-  HIP_TRY(launch_ca_moments(rho, I.p.nx, I.p.ny, b, wall, mid, sx, sy, c->d_partials(), kMeasureBlocks, c->stream));
-  HIP_TRY(hipMemcpyAsync(part.data(), c->d_partials(), sizeof(double) * kMeasureBlocks * kMeasureMoments,
-                         hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  double m[kMeasureMoments] = {0};
-  for (int j = 0; j < kMeasureMoments; ++j)
-    for (int k = 0; k < kMeasureBlocks; ++k) m[j] += part[j * kMeasureBlocks + k];
-  if (m[0] < 3) return fail(LBM_E_INVALID, "too few interface points in the box (%g)", m[0]);
-  // Kasa normal equations for x^2 + y^2 + D x + E y + F = 0.
-  double M3[3][4] = {{m[3], m[5], m[1], -(m[6] + m[7])},
-                     {m[5], m[4], m[2], -(m[8] + m[9])},
-                     {m[1], m[2], m[0], -(m[3] + m[4])}};
-  for (int col = 0; col < 3; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < 3; ++r)
-      if (std::fabs(M3[r][col]) > std::fabs(M3[piv][col])) piv = r;
-    if (M3[piv][col] == 0.0) return fail(LBM_E_INVALID, "degenerate circle fit");
-    if (piv != col)
-      for (int k = 0; k < 4; ++k) std::swap(M3[piv][k], M3[col][k]);
-    for (int r = col + 1; r < 3; ++r) {
-      const double f = M3[r][col] / M3[col][col];
-      for (int k = col; k < 4; ++k) M3[r][k] -= f * M3[col][k];
-    }
-  }
-  double sol[3];
-  for (int r = 2; r >= 0; --r) {
-    double v = M3[r][3];
-    for (int k = r + 1; k < 3; ++k) v -= M3[r][k] * sol[k];
-    sol[r] = v / M3[r][r];
-  }
-  const double xc = -0.5 * sol[0], yc = -0.5 * sol[1];
-  const double R = std::sqrt(xc * xc + yc * yc - sol[2]);
-  const double Xc = xc + sx, Yc = yc + sy;
-  const double yw = wall == 0 ? 0.5 : I.p.ny - 1.5;
-  double cth = wall == 0 ? (yw - Yc) / R : (Yc - yw) / R;
-  cth = std::max(-1.0, std::min(1.0, cth));
-  out[0] = std::acos(cth);
-  out[1] = R;
-  out[2] = Xc;
-  out[3] = Yc;
-  out[4] = m[0];
-  return LBM_OK;
+  return measure_contact_angle_field(rho, I.p.nx, I.p.ny, wall, b, c->d_partials(), c->stream, out);
 }
 
 int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen) {
@@ -980,9 +1047,30 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   for (int i = 0; i < c->n(); ++i) saved[i] = c->inst[i].strip_rows;
   const int saved_waves = c->waves;
   const bool saved_pf = c->prefetch;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  // On every exit: the events are destroyed, and unless the search completed the saved shape comes back with its
+  // task table (the trials uploaded theirs) and no graph of a trial shape survives.
+  struct Guard {
+    lbm_ctx* c;
+    const std::vector<int>& saved;
+    int waves;
+    bool pf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool done = false;
+    ~Guard() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (done) return;
+      c->waves = waves;
+      c->prefetch = pf;
+      for (int i = 0; i < c->n(); ++i) c->inst[i].strip_rows = saved[i];
+      c->build_tasks();
+      (void)c->upload_tables();
+      c->drop_graphs();
+    }
+  } guard{c, saved, saved_waves, saved_pf};
+  HIP_TRY(hipEventCreate(&guard.e0));
+  HIP_TRY(hipEventCreate(&guard.e1));
+  hipEvent_t e0 = guard.e0, e1 = guard.e1;
   auto trial = [&](float* ms) -> int {
     c->build_tasks();
     int rc = c->upload_tables();
@@ -1037,12 +1125,11 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
       for (int i : kv.second) c->inst[i].strip_rows = keep;
     }
   }
-  HIP_TRY(hipEventDestroy(e0));
-  HIP_TRY(hipEventDestroy(e1));
   c->build_tasks();
   int rc = c->upload_tables();
   if (rc != LBM_OK) return rc;
   c->drop_graphs();
+  guard.done = true;
   *chosen = c->inst[inst >= 0 ? inst : sel.front()].strip_rows;
   return LBM_OK;
 }
@@ -1088,6 +1175,27 @@ int lbm_adjoint_step(lbm_ctx* c, int32_t inst, const double* d_state_n, const do
 int lbm_adjoint_step_f32(lbm_ctx* c, int32_t inst, const float* d_state_n, const float* d_lambda_np1,
                          float* d_lambda_n, double* d_theta_bar, double* d_G_bar) {
   return adjoint_step(c, inst, true, d_state_n, d_lambda_np1, d_lambda_n, d_theta_bar, d_G_bar);
+}
+
+namespace {
+int seed_rho(lbm_ctx* c, int32_t inst, bool f32, const double* d_grad_rho, void* d_lambda, double* d_theta_bar,
+             double* d_G_bar) {
+  CHECK_INST(c, inst);
+  if (!d_grad_rho || !d_lambda || !d_theta_bar || !d_G_bar) return fail(LBM_E_INVALID, "NULL buffer");
+  const Inst& I = c->inst[inst];
+  HIP_TRY(launch_adjoint_seed_rho(f32, d_grad_rho, d_lambda, d_theta_bar, d_G_bar, I.p.nx, I.p.ny - 2, c->stream));
+  return LBM_OK;
+}
+}  // namespace
+
+int lbm_adjoint_seed_rho(lbm_ctx* c, int32_t inst, const double* d_grad_rho, double* d_lambda, double* d_theta_bar,
+                         double* d_G_bar) {
+  return seed_rho(c, inst, false, d_grad_rho, d_lambda, d_theta_bar, d_G_bar);
+}
+
+int lbm_adjoint_seed_rho_f32(lbm_ctx* c, int32_t inst, const double* d_grad_rho, float* d_lambda,
+                             double* d_theta_bar, double* d_G_bar) {
+  return seed_rho(c, inst, true, d_grad_rho, d_lambda, d_theta_bar, d_G_bar);
 }
 
 }  // extern "C"

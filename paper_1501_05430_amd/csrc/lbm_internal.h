@@ -107,7 +107,23 @@ hipError_t launch_adjoint(const InstDesc* d_desc, const InstDesc& h, int inst, c
                           const void* f_n, const void* lam_np1, void* lam_n, double* theta_bar, double* G_bar,
                           hipStream_t s);
 
+// lambda_N [9][nyf][nx] (FP32 if f32, else FP64) = grad_rho [nyf][nx] on every plane; theta_bar [2][nx] and G_bar[2]
+// set to zero.
+hipError_t launch_adjoint_seed_rho(bool f32, const double* grad_rho, void* lam, double* theta_bar, double* G_bar,
+                                   int nx, int nyf, hipStream_t s);
+
 constexpr int kMeasureBlocks = 512;
 constexpr int kMeasureMoments = 10;
+// Doubles of reduction partials one contact-angle measurement needs (min/max pass, then the moments pass).
+constexpr int kMeasurePartials = kMeasureBlocks * kMeasureMoments;
+
+// Host part of the contact-angle measurement on a device density field rho [ny][nx] (FP64, ghost rows included),
+// box already clipped to the fluid rows: min/max and moment passes with their partials in d_partials
+// (kMeasurePartials doubles), folded on the host in a fixed order, Kasa fit. Returns an lbm_status and sets
+// lbm_last_error on failure. Synchronizes the stream. Implemented in lbm_api.cpp.
+int measure_contact_angle_field(const double* d_rho, int nx, int ny, int wall, const int32_t box[4],
+                                double* d_partials, hipStream_t s, double out[5]);
+// Sets the message lbm_last_error() returns and passes the status through (lbm_api.cpp).
+int report_error(int code, const char* msg);
 
 }  // namespace lbm

@@ -141,6 +141,12 @@ class LBM:
             keys = ["rho_v", "rho_l", "rho_1", "rho_2", "_", "rho_cap"]
         return dict(zip(keys, list(out)))
 
+    def coexistence(self, inst=0):
+        """(rho_v, rho_l) the library solved for instance inst."""
+        out = (C.c_double * 2)()
+        check(self.lib.lbm_coexistence(self.ctx, inst, out))
+        return out[0], out[1]
+
     def init_droplet(self, xc, yc, R, inst=0, width=5.0, rho_l=0.0, rho_v=0.0):
         xa, xp = _dptr(np.atleast_1d(xc))
         ya, yp = _dptr(np.atleast_1d(yc))
@@ -165,6 +171,14 @@ class LBM:
     # ------------------------------------------------------------------------------------------- stepping
     def step(self, nsteps, inst=0):
         check(self.lib.lbm_step(self.ctx, inst, int(nsteps)))
+
+    def step_timed(self, nsteps, inst=0):
+        """Advance nsteps and return the device time of the queued steps in ms (HIP events on the library's stream).
+        Raises LbmError as step() does."""
+        ms = C.c_double()
+        rc = self.lib.lbm_step_timed(self.ctx, inst, int(nsteps), C.byref(ms))
+        check(rc)
+        return ms.value
 
     def autotune(self, inst=0, trial_steps=20):
         out = C.c_int32()
@@ -265,6 +279,23 @@ class LBM:
         fn = self.lib.lbm_adjoint_step if dt == torch.float64 else self.lib.lbm_adjoint_step_f32
         check(fn(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),
                  C.c_void_p(lam_n.data_ptr()), C.c_void_p(theta_bar.data_ptr()), C.c_void_p(G_bar.data_ptr())))
+        self._hand_over()
+
+    def adjoint_seed_rho(self, grad_rho, lam, theta_bar, G_bar, inst=0):
+        """lam = dL/df_N from grad_rho = dL/drho_N [ny-2, nx] (device FP64) on every population plane; theta_bar and
+        G_bar set to zero. lam is FP64 or FP32 [9, ny-2, nx] (the FP32 form feeds the FP32 adjoint step)."""
+        import torch
+        p = self.params[inst]
+        assert grad_rho.is_cuda and grad_rho.is_contiguous() and grad_rho.dtype == torch.float64
+        assert grad_rho.numel() == (p.ny - 2) * p.nx
+        assert lam.is_cuda and lam.is_contiguous() and lam.dtype in (torch.float64, torch.float32)
+        assert lam.numel() == 9 * (p.ny - 2) * p.nx
+        for t, size in ((theta_bar, 2 * p.nx), (G_bar, 2)):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.numel() == size
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        fn = self.lib.lbm_adjoint_seed_rho if lam.dtype == torch.float64 else self.lib.lbm_adjoint_seed_rho_f32
+        check(fn(self.ctx, inst, C.c_void_p(grad_rho.data_ptr()), C.c_void_p(lam.data_ptr()),
+                 C.c_void_p(theta_bar.data_ptr()), C.c_void_p(G_bar.data_ptr())))
         self._hand_over()
 
     def _hand_over(self):

@@ -17,8 +17,11 @@ def declared_functions():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for must in ["lbm_create", "lbm_init_droplet", "lbm_step", "lbm_apply_wetting", "lbm_measure_contact_angle",
-                 "lbm_adjoint_step"]:
+    # the calls of the method's boundary: its problem statement (a droplet on a wall at a prescribed angle, Sec. 3.1
+    # and 4) plus workspace, state, diagnostics and the adjoint step
+    for must in ["lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_coexistence", "lbm_init_droplet",
+                 "lbm_apply_wetting", "lbm_step", "lbm_measure_contact_angle", "lbm_mass", "lbm_get_rho",
+                 "lbm_get_state", "lbm_set_state", "lbm_adjoint_step", "lbm_last_error"]:
         assert must in names
 
 

@@ -211,8 +211,14 @@ def test_c5_gradient_every_wall_angle_vs_central_fd(c5):
                 vals.append(c5_loss(case, sim, f0, target, b, t))
             fd[wall * nx + c] = (vals[0] - vals[1]) / (2 * h)
     err = np.abs(g - fd).max() / np.abs(fd).max()
-    print(f"\n  c5 all {2 * nx} wall angles: max|g - g_FD| / max|g_FD| = {err:.1e}")
+    # per component, wherever the derivative is resolved: |g_FD| at least 1e-3 of the largest (smaller ones sit at
+    # the finite differences' round-off, ~1e-16 L / h)
+    big = np.abs(fd) >= 1e-3 * np.abs(fd).max()
+    comp = (np.abs(g - fd)[big] / np.abs(fd)[big]).max()
+    print(f"\n  c5 all {2 * nx} wall angles: max|g - g_FD| / max|g_FD| = {err:.1e}; per component "
+          f"({big.sum()} above the floor) max |g - g_FD| / |g_FD| = {comp:.1e}")
     assert err <= 1e-4, err
+    assert comp <= 1e-4, comp
 
 
 def test_c5_gradient_vs_reference_complex_step(ora, c5):
