@@ -26,10 +26,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+# the dominant kernel: the two-step FP32 kernel (two time steps per launch) and the headers it inlines
 KERNEL_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
-              for n in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_f32_c3.json")
-TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step_f32_batched_c4.json")
+              for n in ("lbm_step2.hip", "lbm_device.h", "lbm_internal.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")
+TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step2_f32_batched_c4.json")
 
 
 def kernel_sha():
@@ -220,6 +221,18 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
     batch.step(50, inst=-1)
     ms_b, stable_b = timed_steps(batch, steps_batched, inst=-1)
     batch.close()
+    mlups_b = nodes * steps_batched / ms_b / 1e3
+    ach = 72 * nodes * steps_batched / ms_b / 1e6
+    out = {
+        "instances": len(cases), "fluid_nodes": nodes, "dtype": "f32", "precision": "f32_shifted",
+        "batched_mlups": round(mlups_b, 1), "batched_stable": stable_b,
+        "batched_gbs_alg": round(ach, 1),
+        # the batched launches (all instances in each) against the HBM peak: 72 B per fluid node and step
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": profile_traffic(TRAFFIC_FILE_C4)},
+    }
+    if steps_plain <= 0:
+        return out
     # plain per-instance launches (each instance its own context and graph), same total work per step
     sims = []
     for c, p in zip(cases, params):
@@ -238,20 +251,10 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
     dt_plain = time.perf_counter() - t0
     for s in sims:
         s.close()
-    mlups_b = nodes * steps_batched / ms_b / 1e3
     mlups_p = nodes * steps_plain / dt_plain / 1e6
-    ach = 72 * nodes * steps_batched / ms_b / 1e6
-    traffic = profile_traffic(TRAFFIC_FILE_C4)
-    return {
-        "instances": len(cases), "fluid_nodes": nodes, "dtype": "f32", "precision": "f32_shifted",
-        "batched_mlups": round(mlups_b, 1), "batched_stable": stable_b,
-        "batched_gbs_alg": round(72 * nodes * steps_batched / ms_b / 1e6, 1),
-        "plain_sequential_mlups": round(mlups_p, 1),
-        "speedup": round(mlups_b / mlups_p, 2),
-        # the batched launch (one step of all instances) against the HBM peak: 72 B per fluid node
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic},
-    }
+    out["plain_sequential_mlups"] = round(mlups_p, 1)
+    out["speedup"] = round(mlups_b / mlups_p, 2)
+    return out
 
 
 def adjoint_rate(case, calls=30, dtype="f64", **kw):
@@ -315,6 +318,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the step kernel's block shape first (default: the library's defaults)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 256-instance batched leg and print its JSON (for profiling that launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the method on a single MI355X "
@@ -326,6 +331,10 @@ def main():
     from paper_1501_05430_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.load()
+
+    if args.batched_only:
+        print(json.dumps({"batched_256": batched_vs_plain(steps_batched=args.steps, steps_plain=0)}), flush=True)
+        return
 
     case = W.c3_large()
     ceilings = bandwidth_ceilings(case.nx, case.ny)

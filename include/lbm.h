@@ -84,12 +84,17 @@ typedef struct {
   int32_t precision;      /* lbm_precision; every instance of a context must use the same one */
   int32_t wet_iters;      /* 0: Eq. 19; k >= 1: k-th iterate of Eq. 21 (first line = iterate 1) [4] */
   int32_t check_every;    /* steps between device checks of mass, non-finite density and clamps; 0 = none */
-  int32_t strip_rows;     /* rows per block strip of the step kernel; 0 = library default: about two blocks per
-                             compute unit over all instances, 2..32 rows (FP32) / 2..64 (FP64) */
+  int32_t strip_rows;     /* rows per block strip of the step kernels; 0 = library default: for the one-step
+                             kernel about two blocks per compute unit over all instances, 2..32 rows (FP32) / 2..64
+                             (FP64); 32 output rows for the two-step kernel */
   int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step (any precision) */
-  int32_t step_variant;   /* step kernel shape: k = 1..4 selects 1, 2, 4 or 8 wavefronts (64, 128, 256 or 512
-                             aligned columns) per block; 0 = library default. Instance 0's value applies to the
-                             whole context (lbm_autotune may change it). Results do not depend on it (bitwise). */
+  int32_t step_variant;   /* step kernel shape: k = 1..4 selects the one-step kernel with 1, 2, 4 or 8 wavefronts
+                             (64, 128, 256 or 512 aligned columns) per block, 5..8 the same with the next row's
+                             loads in flight; 9..12 the two-step kernel (two time steps per launch, FP32, tau = 1
+                             BGK with geometric walls; other selections step one at a time) with 1, 2, 4 or 8
+                             wavefronts per block; 0 = library default (two-step for FP32 where it applies).
+                             Instance 0's value applies to the whole context (lbm_autotune may change it). Results
+                             do not depend on it (bitwise). */
   int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y] */
   int32_t eos;            /* lbm_eos [LBM_EOS_CARNAHAN_STARLING] */
   double tau;             /* BGK relaxation time (> 0.5) [1.0] */

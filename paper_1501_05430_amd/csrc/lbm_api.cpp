@@ -224,6 +224,11 @@ constexpr int kDefaultStripRows64 = 64;
 constexpr int kDefaultWaves64 = 4;
 constexpr bool kDefaultPrefetch64 = false;
 constexpr int kMinDefaultStripRows = 2;
+// Two-step kernel (lbm_step2.hip): wavefronts per block and output rows per strip.
+constexpr int kDefaultWaves2 = 4;
+constexpr int kDefaultStripRows2 = 32;
+constexpr int kMinStripRows2 = 8, kMaxStripRows2 = 256;  // bounds of the default from the occupancy
+constexpr int kStep2Halo = 6;  // step A columns beyond a two-step tile's outputs (three per side)
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
 static_assert(sizeof(lbm_params) == 10 * 4 + 22 * 8, "lbm_params layout: 10 int32 then 22 double, no padding");
@@ -235,6 +240,7 @@ struct Inst {
   double rho_c = 0, T_c = 0, T = 0, rho_v = 0, rho_l = 0, rho_cap = 0;
   double pw_r1 = 0, pw_r2 = 0;  // piecewise-linear EOS break points
   int strip_rows = kDefaultStripRows;
+  int strip_rows2 = kDefaultStripRows2;  // output rows per strip of the two-step kernel
   bool initialized = false;
   int64_t steps = 0;
   size_t off_f[2] = {0, 0}, off_th = 0, off_ghost = 0, off_adj = 0;
@@ -242,8 +248,8 @@ struct Inst {
 };
 
 struct Layout {
-  size_t desc, tasks, wdiag, first, idiag, drops, rho_scratch, partials, total;
-  size_t task_cap;
+  size_t desc, tasks, wdiag, first, idiag, drops, rho_scratch, partials, tasks2, total;
+  size_t task_cap, task2_cap;
   std::vector<size_t> inst_f[2], inst_th, inst_ghost, inst_adj;
 };
 
@@ -277,7 +283,7 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.wet_iters < 0 || q.wet_iters > 1000) return bad("wet_iters out of range [0, 1000]");
     if (q.check_every < 0) return bad("check_every < 0");
     if (q.strip_rows < 0) return bad("strip_rows < 0");
-    if (q.step_variant < 0 || q.step_variant > 2 * kNumWaveChoices) return bad("step_variant outside [0, 8]");
+    if (q.step_variant < 0 || q.step_variant > 3 * kNumWaveChoices) return bad("step_variant outside [0, 12]");
     if (q.boundary != LBM_WALLS_Y && q.boundary != LBM_PERIODIC_Y && q.boundary != LBM_WALLS_MARTYS_CHEN)
       return bad("unknown boundary");
     if (!std::isfinite(q.G_w[0]) || !std::isfinite(q.G_w[1])) return bad("G_w not finite");
@@ -324,9 +330,11 @@ Layout make_layout(const lbm_params* p, int32_t n) {
     return r;
   };
   L.task_cap = 0;
+  L.task2_cap = 0;
   size_t max_nodes = 0;
   for (int i = 0; i < n; ++i) {
     L.task_cap += (size_t)blocks_x(p[i].nx, 1) * (size_t)(p[i].ny - 2);
+    L.task2_cap += (size_t)((p[i].nx + (64 - kStep2Halo) - 1) / (64 - kStep2Halo)) * (size_t)(p[i].ny - 2);
     max_nodes = std::max(max_nodes, (size_t)p[i].nx * p[i].ny);
   }
   L.desc = take(sizeof(InstDesc) * n);
@@ -337,6 +345,7 @@ Layout make_layout(const lbm_params* p, int32_t n) {
   L.drops = take(sizeof(double) * 3 * kMaxDrops);
   L.rho_scratch = take(sizeof(double) * max_nodes);
   L.partials = take(sizeof(double) * kMeasureBlocks * 16);
+  L.tasks2 = take(sizeof(WaveTask) * L.task2_cap);
   for (int i = 0; i < n; ++i) {
     const size_t pitch = (size_t)((p[i].nx + 63) / 64 * 64);
     const size_t fbytes = storage_bytes(p[i].precision) * 9 * pitch * (size_t)(p[i].ny - 2);
@@ -427,11 +436,21 @@ struct lbm_ctx {
   std::vector<InstDesc> hdesc;
   std::vector<int32_t> first;       // [n+1] task ranges per instance
   std::vector<WaveTask> tasks;
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (selection, length, final check) -> graph
+  // two steps per launch where the selection allows it (FP32, tau = 1 BGK, geometric walls)
+  bool step2 = false;
+  int waves2 = kDefaultWaves2;
+  std::vector<int32_t> first2;      // [n+1] ranges of the two-step tasks
+  std::vector<WaveTask> tasks2;
+  struct Chunk {
+    hipGraphExec_t ex;
+    int64_t launches;  // kernel launches of the step kernels in the graph (each flips the buffers once)
+  };
+  std::map<std::tuple<int, int, int>, Chunk> graphs;  // (selection, length, final check) -> graph
   hipEvent_t ev[2] = {nullptr, nullptr};  // lbm_step_timed: around the queued steps
 
   InstDesc* d_desc() { return (InstDesc*)(ws + L.desc); }
   WaveTask* d_tasks() { return (WaveTask*)(ws + L.tasks); }
+  WaveTask* d_tasks2() { return (WaveTask*)(ws + L.tasks2); }
   WaveDiag* d_wdiag() { return (WaveDiag*)(ws + L.wdiag); }
   int32_t* d_first() { return (int32_t*)(ws + L.first); }
   InstDiag* d_idiag() { return (InstDiag*)(ws + L.idiag); }
@@ -446,8 +465,16 @@ struct lbm_ctx {
     return true;
   }
 
+  // the two-step kernel covers the selection: FP32 storage, tau = 1 BGK and geometric walls everywhere
+  bool step2_ok(int sel) const {
+    if (!step2 || storage != STORE_F32 || !tau1(sel)) return false;
+    for (int i = 0; i < n(); ++i)
+      if ((sel < 0 || i == sel) && inst[i].p.boundary != LBM_WALLS_Y) return false;
+    return true;
+  }
+
   void drop_graphs() {
-    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second.ex);
     graphs.clear();
   }
 
@@ -482,11 +509,44 @@ struct lbm_ctx {
       }
     }
     first[n()] = (int)tasks.size();
+    build_tasks2();
+  }
+
+  // Two-step tiles: ceil(nx / (64 waves2 - 6)) column tiles of balanced width, rows balanced over
+  // ceil((ny-2)/strip_rows2) bands; bands outer, tiles inner (the kernel hands contiguous runs of this table to
+  // one XCD each).
+  void build_tasks2() {
+    tasks2.clear();
+    first2.assign(n() + 1, 0);
+    const int wmax = 64 * waves2 - kStep2Halo;
+    for (int i = 0; i < n(); ++i) {
+      first2[i] = (int)tasks2.size();
+      const int nx = inst[i].p.nx, nyf = inst[i].p.ny - 2;
+      const int nt = (nx + wmax - 1) / wmax;
+      const int H = std::max(1, std::min(inst[i].strip_rows2, nyf));
+      const int sy = (nyf + H - 1) / H;
+      for (int b = 0; b < sy; ++b) {
+        const int ya = 1 + (int)((int64_t)nyf * b / sy), yb = 1 + (int)((int64_t)nyf * (b + 1) / sy);
+        for (int a = 0; a < nt; ++a) {
+          const int xa = (int)((int64_t)nx * a / nt), xb = (int)((int64_t)nx * (a + 1) / nt);
+          WaveTask t;
+          t.inst = i;
+          t.x0 = xa;
+          t.y0 = ya;
+          t.wh = (xb - xa) | ((yb - ya) << 16);
+          tasks2.push_back(t);
+        }
+      }
+    }
+    first2[n()] = (int)tasks2.size();
   }
 
   int upload_tables() {
-    if (tasks.size() > L.task_cap) return fail(LBM_E_INVALID, "task table overflow");
+    if (tasks.size() > L.task_cap || tasks2.size() > L.task2_cap) return fail(LBM_E_INVALID, "task table overflow");
     HIP_TRY(hipMemcpyAsync(d_tasks(), tasks.data(), sizeof(WaveTask) * tasks.size(), hipMemcpyHostToDevice, stream));
+    if (!tasks2.empty())
+      HIP_TRY(hipMemcpyAsync(d_tasks2(), tasks2.data(), sizeof(WaveTask) * tasks2.size(), hipMemcpyHostToDevice,
+                             stream));
     HIP_TRY(hipMemcpyAsync(d_first(), first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(d_desc(), hdesc.data(), sizeof(InstDesc) * hdesc.size(), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -527,9 +587,15 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     c->waves = kDefaultWaves64;
     c->prefetch = kDefaultPrefetch64;
   }
-  if (p[0].step_variant > 0) {
+  // two steps per launch by default for FP32 (where the selection allows it); variants 1..8 choose a one-step
+  // shape, 9..12 the two-step kernel with 1, 2, 4 or 8 wavefronts per block
+  c->step2 = c->storage == STORE_F32;
+  if (p[0].step_variant > 0 && p[0].step_variant <= 2 * kNumWaveChoices) {
     c->waves = kWaveChoices[(p[0].step_variant - 1) % kNumWaveChoices];
     c->prefetch = (p[0].step_variant - 1) / kNumWaveChoices == 1;
+    c->step2 = false;
+  } else if (p[0].step_variant > 2 * kNumWaveChoices) {
+    c->waves2 = kWaveChoices[p[0].step_variant - 2 * kNumWaveChoices - 1];
   }
   c->inst.resize(n_inst);
   c->hdesc.resize(n_inst);
@@ -540,6 +606,7 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     I.plane = (int64_t)I.pitch * (p[i].ny - 2);
     I.strip_rows = p[i].strip_rows > 0 ? p[i].strip_rows
                                         : (p[i].precision == LBM_F64 ? kDefaultStripRows64 : kDefaultStripRows);
+    I.strip_rows2 = p[i].strip_rows > 0 ? p[i].strip_rows : kDefaultStripRows2;
     PwEos pw{};
     if (p[i].eos == LBM_EOS_PIECEWISE_LINEAR) {
       pw_from_params(p[i], &pw);  // solvable: checked by valid_params
@@ -626,6 +693,18 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
                                       std::min<long>(hmax, std::lround(nodes / (2.0 * cus * 64 * c->waves))));
     for (int i = 0; i < n_inst; ++i)
       if (p[i].strip_rows <= 0) c->inst[i].strip_rows = h;
+    // two-step kernel: one round of resident blocks over all instances, each task a tile of a strip; fewer, taller
+    // strips than that leave compute units idle, more add a partial second round and more halo rows
+    int per_cu = 0;
+    if (c->storage == STORE_F32 && step2_blocks_per_cu(c->waves2, &per_cu) == hipSuccess && per_cu > 0) {
+      const int wmax = 64 * c->waves2 - kStep2Halo;
+      double tile_rows = 0;
+      for (int i = 0; i < n_inst; ++i) tile_rows += (double)((p[i].nx + wmax - 1) / wmax) * (p[i].ny - 2);
+      const int h2 = (int)std::max<long>(kMinStripRows2, std::min<long>(kMaxStripRows2,
+                                         (long)std::ceil(tile_rows / ((double)cus * per_cu))));
+      for (int i = 0; i < n_inst; ++i)
+        if (p[i].strip_rows <= 0) c->inst[i].strip_rows2 = h2;
+    }
   }
   c->build_tasks();
   int rc = c->upload_tables();
@@ -756,22 +835,38 @@ int lbm_apply_wetting(lbm_ctx* c, int32_t inst, const double* theta_bottom, cons
 
 namespace {
 
-// Queue `count` steps for the selection (task range), flips starting at 0, checks every K (0 = none) counting
-// from the first queued step, plus one after the last step if final_check.
-int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check) {
+// Queue `count` steps for the selection (task range), buffer flips starting at 0, checks every K (0 = none)
+// counting from the first queued step, plus one after the last step if final_check. Two unchecked steps in a row
+// go into one two-step launch where the selection allows it; checked steps are one-step launches (the check reads
+// the launch's input state). Each launch flips the buffers once. *launches receives the launch count; dry = true
+// only counts.
+int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check, int64_t* launches, bool dry = false) {
   const int a = sel < 0 ? 0 : c->first[sel];
   const int b = sel < 0 ? c->first[c->n()] : c->first[sel + 1];
+  const int a2 = sel < 0 ? 0 : c->first2[sel];
+  const int b2 = sel < 0 ? c->first2[c->n()] : c->first2[sel + 1];
   const int ninst = sel < 0 ? c->n() : 1;
   const int inst0 = sel < 0 ? 0 : sel;
-  for (int64_t i = 0; i < count; ++i) {
-    const bool chk = (K > 0 && (i + 1) % K == 0) || (final_check && i == count - 1);
-    HIP_TRY(launch_step(c->storage, chk, c->tau1(sel), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a, b - a, (int)(i & 1),
-                        c->d_wdiag() + a,
-                        c->stream));
-    if (chk)
-      HIP_TRY(launch_finalize_diag(c->d_tasks(), c->d_first(), ninst, inst0, c->d_wdiag(), c->d_idiag(),
-                                   c->d_desc(), c->stream));
+  const bool two = c->step2_ok(sel);
+  auto chk_at = [&](int64_t i) { return (K > 0 && (i + 1) % K == 0) || (final_check && i == count - 1); };
+  int64_t nl = 0;
+  for (int64_t i = 0; i < count; ++nl) {
+    const bool chk = chk_at(i);
+    if (two && !chk && i + 1 < count && !chk_at(i + 1)) {
+      if (!dry) HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, (int)(nl & 1), c->stream));
+      i += 2;
+      continue;
+    }
+    if (!dry) {
+      HIP_TRY(launch_step(c->storage, chk, c->tau1(sel), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a, b - a,
+                          (int)(nl & 1), c->d_wdiag() + a, c->stream));
+      if (chk)
+        HIP_TRY(launch_finalize_diag(c->d_tasks(), c->d_first(), ninst, inst0, c->d_wdiag(), c->d_idiag(),
+                                     c->d_desc(), c->stream));
+    }
+    i += 1;
   }
+  *launches = nl;
   return LBM_OK;
 }
 
@@ -779,7 +874,7 @@ int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check) {
 // remainder of a call, so a bounded number of them is kept.
 constexpr size_t kMaxGraphs = 64;
 
-int get_graph(lbm_ctx* c, int sel, int len, int K, bool final_check, hipGraphExec_t* out) {
+int get_graph(lbm_ctx* c, int sel, int len, int K, bool final_check, lbm_ctx::Chunk* out) {
   auto key = std::make_tuple(sel, len, final_check ? 1 : 0);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
@@ -787,12 +882,13 @@ int get_graph(lbm_ctx* c, int sel, int len, int K, bool final_check, hipGraphExe
     return LBM_OK;
   }
   if (c->graphs.size() >= kMaxGraphs) {
-    *out = nullptr;  // the caller queues plain launches
+    *out = lbm_ctx::Chunk{nullptr, 0};  // the caller queues plain launches
     return LBM_OK;
   }
   hipGraph_t g = nullptr;
+  int64_t nl = 0;
   HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  int rc = queue_steps(c, sel, len, K, final_check);
+  int rc = queue_steps(c, sel, len, K, final_check, &nl);
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (rc != LBM_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -803,8 +899,8 @@ int get_graph(lbm_ctx* c, int sel, int len, int K, bool final_check, hipGraphExe
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(LBM_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
-  c->graphs[key] = ex;
-  *out = ex;
+  c->graphs[key] = lbm_ctx::Chunk{ex, nl};
+  *out = c->graphs[key];
   return LBM_OK;
 }
 
@@ -824,34 +920,43 @@ int step_impl(lbm_ctx* c, int32_t inst, int64_t nsteps, hipEvent_t* ev) {
   if (ev) HIP_TRY(hipEventRecord(ev[0], c->stream));
   if (nsteps > 0) {
     const int K = c->inst[inst < 0 ? 0 : inst].p.check_every;
-    const int len = K > 0 ? (K % 2 == 0 ? K : 2 * K) : 64;
-    int64_t left = nsteps;
+    // chunk length: whole check periods with an even number of launches, so that every replay starts from the
+    // same buffer with the same check positions
+    int len = K > 0 ? (K % 2 == 0 ? K : 2 * K) : 64;
+    int64_t nl_len = 0;
+    queue_steps(c, inst, len, K, false, &nl_len, true);
+    if (nl_len & 1) len *= 2;
+    int64_t left = nsteps, launches = 0;
     const bool graphs = c->stream != nullptr && len <= 4096;
     if (graphs && nsteps >= len) {
-      hipGraphExec_t ex;
-      int rc = get_graph(c, inst, len, K, false, &ex);
+      lbm_ctx::Chunk ch;
+      int rc = get_graph(c, inst, len, K, false, &ch);
       if (rc != LBM_OK) return rc;
-      while (ex && left >= len) {
-        HIP_TRY(hipGraphLaunch(ex, c->stream));
+      while (ch.ex && left >= len) {
+        HIP_TRY(hipGraphLaunch(ch.ex, c->stream));
         left -= len;
+        launches += ch.launches;
       }
     }
-    // The rest (fewer steps than a chunk; graph replays cover a multiple of 2 K steps, so flips restart at 0 and
-    // check positions stay aligned): one graph of exactly that length, or plain launches once the cache is full.
+    // The rest (fewer steps than a chunk): one graph of exactly that length, or plain launches once the cache is
+    // full. Chunk replays end on the starting buffer, so its flips restart at 0 and check positions stay aligned.
     if (left > 0 && graphs && left < len) {
-      hipGraphExec_t ex;
-      int rc = get_graph(c, inst, (int)left, K, K > 0, &ex);
+      lbm_ctx::Chunk ch;
+      int rc = get_graph(c, inst, (int)left, K, K > 0, &ch);
       if (rc != LBM_OK) return rc;
-      if (ex) {
-        HIP_TRY(hipGraphLaunch(ex, c->stream));
+      if (ch.ex) {
+        HIP_TRY(hipGraphLaunch(ch.ex, c->stream));
+        launches += ch.launches;
         left = 0;
       }
     }
     if (left > 0) {
-      int rc = queue_steps(c, inst, left, K, K > 0);
+      int64_t nl = 0;
+      int rc = queue_steps(c, inst, left, K, K > 0, &nl);
       if (rc != LBM_OK) return rc;
+      launches += nl;
     }
-    if (nsteps & 1) {
+    if (launches & 1) {
       for (int i = 0; i < c->n(); ++i) {
         if (inst >= 0 && i != inst) continue;
         c->hdesc[i].cur ^= 1;
@@ -1031,7 +1136,8 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   for (int i = 0; i < c->n(); ++i)
     if ((inst < 0 || i == inst) && !c->inst[i].initialized) return fail(LBM_E_STATE, "instance %d has no state", i);
   // The selection is timed as it runs: one launch over all its tasks. Trial launches read the state buffer and
-  // write the spare one (flip 0), walking up and down alternately, so the state is not modified.
+  // write the spare one (flip 0), walking up and down alternately, so the state is not modified. Times are compared
+  // per time step (a two-step launch counts twice).
   std::vector<int> sel;
   int max_nx = 0, max_nyf = 0;
   for (int i = 0; i < c->n(); ++i)
@@ -1043,17 +1149,20 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   std::map<std::pair<int, int>, std::vector<int>> shapes;  // shape classes of the selection
   for (int i : sel) shapes[{c->inst[i].p.nx, c->inst[i].p.ny}].push_back(i);
   const int cand[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 128};
-  std::vector<int> saved(c->n());
-  for (int i = 0; i < c->n(); ++i) saved[i] = c->inst[i].strip_rows;
-  const int saved_waves = c->waves;
-  const bool saved_pf = c->prefetch;
-  // On every exit: the events are destroyed, and unless the search completed the saved shape comes back with its
-  // task table (the trials uploaded theirs) and no graph of a trial shape survives.
+  const int cand2[] = {8, 12, 16, 24, 32, 40, 48, 56, 64, 96, 128};
+  std::vector<int> saved(c->n()), saved2(c->n());
+  for (int i = 0; i < c->n(); ++i) {
+    saved[i] = c->inst[i].strip_rows;
+    saved2[i] = c->inst[i].strip_rows2;
+  }
+  // On every exit: the events are destroyed, and unless the search completed the saved shapes come back with their
+  // task tables (the trials uploaded theirs) and no graph of a trial shape survives.
   struct Guard {
     lbm_ctx* c;
     const std::vector<int>& saved;
-    int waves;
-    bool pf;
+    const std::vector<int>& saved2;
+    int waves, waves2;
+    bool pf, step2;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool done = false;
     ~Guard() {
@@ -1062,35 +1171,47 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
       if (done) return;
       c->waves = waves;
       c->prefetch = pf;
-      for (int i = 0; i < c->n(); ++i) c->inst[i].strip_rows = saved[i];
+      c->waves2 = waves2;
+      c->step2 = step2;
+      for (int i = 0; i < c->n(); ++i) {
+        c->inst[i].strip_rows = saved[i];
+        c->inst[i].strip_rows2 = saved2[i];
+      }
       c->build_tasks();
       (void)c->upload_tables();
       c->drop_graphs();
     }
-  } guard{c, saved, saved_waves, saved_pf};
+  } guard{c, saved, saved2, c->waves, c->waves2, c->prefetch, c->step2};
   HIP_TRY(hipEventCreate(&guard.e0));
   HIP_TRY(hipEventCreate(&guard.e1));
   hipEvent_t e0 = guard.e0, e1 = guard.e1;
-  auto trial = [&](float* ms) -> int {
+  // ms per time step of the current shape: one-step launches, or (two = true) two-step launches
+  auto trial = [&](bool two, float* ms) -> int {
     c->build_tasks();
     int rc = c->upload_tables();
     if (rc != LBM_OK) return rc;
     const int a = c->first[sel.front()], b = c->first[sel.back() + 1];
-    for (int k = 0; k <= trial_steps; ++k) {
+    const int a2 = c->first2[sel.front()], b2 = c->first2[sel.back() + 1];
+    const int launches = two ? std::max(1, trial_steps / 2) : trial_steps;
+    for (int k = 0; k <= launches; ++k) {
       if (k == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // launch 0 warms up
-      HIP_TRY(launch_step(c->storage, false, c->tau1(inst), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a,
-                          b - a, 0, c->d_wdiag() + a, c->stream, k & 1));
+      if (two)
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, 0, c->stream));
+      else
+        HIP_TRY(launch_step(c->storage, false, c->tau1(inst), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a,
+                            b - a, 0, c->d_wdiag() + a, c->stream, k & 1));
     }
     HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(hipEventSynchronize(e1));
     *ms = 0;
     HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    *ms /= (float)(two ? 2 * launches : launches);
     return LBM_OK;
   };
-  // 1. wavefronts per block, prefetch and one strip height for the whole selection
+  // 1. one-step kernel: wavefronts per block, prefetch and one strip height for the whole selection
   float best = 1e30f;
-  int best_w = saved_waves, best_h = saved[sel.front()];
-  bool best_pf = saved_pf;
+  int best_w = c->waves, best_h = saved[sel.front()];
+  bool best_pf = c->prefetch;
   for (int pf = 0; pf < 2; ++pf)
     for (int wi = 0; wi < kNumWaveChoices; ++wi) {
       const int w = kWaveChoices[wi];
@@ -1101,7 +1222,7 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
         c->prefetch = pf == 1;
         for (int i : sel) c->inst[i].strip_rows = h;
         float ms;
-        int rc = trial(&ms);
+        int rc = trial(false, &ms);
         if (rc != LBM_OK) return rc;
         if (ms < best) { best = ms; best_w = w; best_pf = pf == 1; best_h = h; }
       }
@@ -1109,20 +1230,46 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   c->waves = best_w;
   c->prefetch = best_pf;
   for (int i : sel) c->inst[i].strip_rows = best_h;
+  // 1b. two-step kernel where the selection allows it: wavefronts per block and one strip height
+  bool use2 = false;
+  c->step2 = true;
+  if (c->step2_ok(inst)) {
+    float best2 = 1e30f;
+    int bw2 = c->waves2, bh2 = saved2[sel.front()];
+    for (int wi = 0; wi < kNumWaveChoices; ++wi) {
+      const int w = kWaveChoices[wi];
+      if (w > 1 && 64 * (w / 2) - kStep2Halo >= max_nx) continue;
+      for (int h : cand2) {
+        if (h > max_nyf && h != cand2[0]) continue;
+        c->waves2 = w;
+        for (int i : sel) c->inst[i].strip_rows2 = h;
+        float ms;
+        int rc = trial(true, &ms);
+        if (rc != LBM_OK) return rc;
+        if (ms < best2) { best2 = ms; bw2 = w; bh2 = h; }
+      }
+    }
+    c->waves2 = bw2;
+    for (int i : sel) c->inst[i].strip_rows2 = bh2;
+    use2 = best2 < best;
+    if (use2) best = best2;
+  }
+  c->step2 = use2 || (c->storage == STORE_F32 && guard.step2 && !c->step2_ok(inst));
   // 2. with several shape classes, refine each class's strip height in turn (the others held)
   if (shapes.size() > 1) {
     for (auto& kv : shapes) {
       const int nyf = kv.first.second - 2;
-      int keep = c->inst[kv.second.front()].strip_rows;
-      for (int h : cand) {
-        if ((h > nyf && h != cand[0]) || h == keep) continue;
-        for (int i : kv.second) c->inst[i].strip_rows = h;
+      int keep = use2 ? c->inst[kv.second.front()].strip_rows2 : c->inst[kv.second.front()].strip_rows;
+      for (int h : use2 ? std::vector<int>(std::begin(cand2), std::end(cand2))
+                        : std::vector<int>(std::begin(cand), std::end(cand))) {
+        if ((h > nyf && h != (use2 ? cand2[0] : cand[0])) || h == keep) continue;
+        for (int i : kv.second) (use2 ? c->inst[i].strip_rows2 : c->inst[i].strip_rows) = h;
         float ms;
-        int rc = trial(&ms);
+        int rc = trial(use2, &ms);
         if (rc != LBM_OK) return rc;
         if (ms < best) { best = ms; keep = h; }
       }
-      for (int i : kv.second) c->inst[i].strip_rows = keep;
+      for (int i : kv.second) (use2 ? c->inst[i].strip_rows2 : c->inst[i].strip_rows) = keep;
     }
   }
   c->build_tasks();
@@ -1130,7 +1277,8 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   if (rc != LBM_OK) return rc;
   c->drop_graphs();
   guard.done = true;
-  *chosen = c->inst[inst >= 0 ? inst : sel.front()].strip_rows;
+  const int i0 = inst >= 0 ? inst : sel.front();
+  *chosen = use2 ? c->inst[i0].strip_rows2 : c->inst[i0].strip_rows;
   return LBM_OK;
 }
 

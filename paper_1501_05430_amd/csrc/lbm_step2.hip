@@ -1,0 +1,344 @@
+// Two time steps per launch (temporal blocking) for the FP32 step with tau = 1 BGK-Guo collision and the geometric
+// walls of Sec. 4: the headline form of the method. Per lattice update it moves about half the HBM bytes of the
+// one-step kernel (lbm_kernels.hip), whose per-node arithmetic it repeats exactly: the results are bit for bit
+// those of two one-step launches.
+//
+// A block of W wavefronts owns a tile: output columns [x0, x0 + bw) (bw <= 64 W - 6) of output rows [y0, ylast].
+// Lane l works on column x0 - 3 + l (periodic), so the tile carries three halo columns on each side.
+//  * Step A (t -> t+1) is the one-step kernel's row walk over all 64 W lanes: the populations g^t are gathered from
+//    HBM (pull scheme with halfway bounce-back), psi (Eq. 10) is exchanged with the neighbouring lanes, and the
+//    force (Eq. 9) and the collision (Eq. 1-6 at tau = 1) produce g^{t+1} of one row per iteration. The ghost rows
+//    (Eq. 19 / 21) are computed where the walk meets a wall, as in the one-step kernel. g^{t+1} does not go to HBM:
+//    it goes into a three-row ring in LDS.
+//  * Step B (t+1 -> t+2) trails two rows behind: it gathers f^{t+1} of row y-1 from the ring (lanes 1 .. 64 W - 2),
+//    forms rho and psi (psi into a three-row LDS ring of its own), computes its own ghost rows from those densities
+//    at a wall, and collides row y-2 on the output lanes, storing g^{t+2} to HBM.
+// Reach: one step reads populations one column away and psi one more, and a ghost row reads densities one column
+// further, so step B's outputs need step A on three more columns per side; step A's own halo (two columns) is
+// gathered by its edge lanes as in the one-step kernel. In y a strip reads g^t rows y0 - 4 .. ylast + 4.
+// Per launch and output node: 36 B read (plus the halo share) and 36 B written for two updates.
+// Block order: consecutive tasks (tiles of one row band, then the next band) are given to the same XCD, so tiles
+// that share halo rows and boundary cache lines meet in one L2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kXcds = 8;
+
+template <int W>
+__global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__ descs,
+                                                    const WaveTask* __restrict__ tasks, int ntasks, int flip) {
+  typedef float C;
+  typedef float S;
+  typedef typename Gbl<S>::T GS;
+  constexpr int L = WAVE * W;
+  // XCD-aware order: blocks go round-robin to the XCDs; XCD k takes the k-th contiguous share of the task table.
+  const int per = (ntasks + kXcds - 1) / kXcds;
+  const int task = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (task >= ntasks) return;  // uniform over the block
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = uni((int)(threadIdx.x >> 6));
+  const WaveTask t = tasks[task];
+  const int inst = uni(t.inst);
+  const InstDesc& d = descs[inst];
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch, iters = d.wet_iters;
+  const int64_t plane = d.plane;
+  const int cur = d.cur ^ flip;
+  const GS* __restrict__ gin = (const GS*)d.f[cur];
+  GS* __restrict__ gout = (GS*)d.f[cur ^ 1];
+  const GCD* __restrict__ cos_th = (const GCD*)d.cos_th;
+  const GCD* __restrict__ cot_th = (const GCD*)d.cot_th;
+  const int x0 = uni(t.x0), y0 = uni(t.y0), bw = uni(t.wh & 0xffff), nrows = uni(t.wh >> 16);
+  const int ylast = y0 + nrows - 1;
+  const C rho0 = (C)d.rho0;
+  auto wrapc = [&](int x) { x %= nx; return x < 0 ? x + nx : x; };
+
+  const int bwA = bw + 6;           // step A's columns: x0 - 3 .. x0 + bw + 2
+  const int lx = wv * WAVE + lane;  // position in the tile = column - (x0 - 3)
+  const bool act = lx < bwA;
+  const int col = wrapc(x0 - 3 + (act ? lx : 0));
+  const bool ledge = lx == 0, redge = lx == bwA - 1;
+  const bool edge = ledge || redge;
+  const int hcol = wrapc(ledge ? x0 - 4 : x0 + bw + 3);  // step A's halo column, gathered by an edge lane
+  const int ocol = wrapc(ledge ? x0 - 5 : x0 + bw + 4);  // one further out (ghost tangential difference)
+  const bool actBg = act && lx >= 1 && lx <= bwA - 2;     // step B gathers here
+  const bool actBw = act && lx >= 2 && lx <= bwA - 3;     // step B ghost rows here
+  const bool actBc = lx >= 3 && lx < bw + 3;              // step B output lanes
+
+  // LDS: step A's post-collision rows (ring of 3 rows), row exchange buffers, step B's psi rows (ring of 3 rows,
+  // ghost rows included) and step B's boundary-row densities (bottom, top) for its ghost rows.
+  __shared__ C gA[3][9][L];
+  __shared__ C xa[2][L + 2];
+  __shared__ C psB[3][L];
+  __shared__ C rhB[2][L];
+
+  // (left, right) neighbours of a per-lane value through xa: put, barrier, get. Edge lanes hold the halo value h.
+  int par = 0;
+  auto xput = [&](C v, C h) {
+    if (act) xa[par][lx + 1] = v;
+    if (ledge) xa[par][0] = h;
+    if (redge) xa[par][bwA + 1] = h;
+  };
+  auto xget = [&](C& l, C& r) {
+    l = xa[par][lx];
+    r = xa[par][lx + 2];
+    par ^= 1;
+  };
+  auto xchg = [&](C v, C h, C& l, C& r) {
+    xput(v, h);
+    __syncthreads();
+    xget(l, r);
+  };
+
+  // ---------------------------------------------------------------------------------------------- step A
+  auto produce = [&](int y, C (&f)[9], C& rho, C& psi, C& hrho, C& hpsi, bool& cl) {
+    if (act) {
+      gather<S, C>(gin, plane, pitch, nx, ny, col, y, f);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = (C)0;
+    }
+    rho = rho0 + sum9(f);
+    psi = psi_eval(d, rho, cl);
+    hrho = (C)0;
+    hpsi = (C)0;
+    if (edge) {
+      C g[9];
+      gather<S, C>(gin, plane, pitch, nx, ny, hcol, y, g);
+      hrho = rho0 + sum9(g);
+      bool dm;
+      hpsi = psi_eval(d, hrho, dm);
+    }
+  };
+  // ghost row beside wall `wall` from the boundary row yb (r1, halo hr1) and the second row (r2, hr2), Sec. 4
+  auto ghostA = [&](int wall, int yb, C r1, C r2, C hr1, C hr2, C& g_rho, C& g_psi, C& gh_psi) {
+    C Lf, Rf;
+    xchg(r1, hr1, Lf, Rf);
+    C ro = (C)0;
+    if (edge) {
+      C g[9];
+      gather<S, C>(gin, plane, pitch, nx, ny, ocol, yb, g);
+      ro = rho0 + sum9(g);
+    }
+    const int base = wall * nx;
+    double r0 = 0.0, rh0 = 0.0;
+    bool gc = false, gch = false;
+    if (act)
+      r0 = ghost_density((double)Lf, (double)Rf, (double)r1, (double)r2, cos_th[base + col], cot_th[base + col],
+                         iters, d.rho_cap_hi, gc);
+    if (edge) {
+      const double hl = ledge ? (double)ro : (double)r1;
+      const double hr = ledge ? (double)r1 : (double)ro;
+      rh0 = ghost_density(hl, hr, (double)hr1, (double)hr2, cos_th[base + hcol], cot_th[base + hcol], iters,
+                          d.rho_cap_hi, gch);
+    }
+    bool dm;
+    g_rho = (C)r0;
+    g_psi = (C)psi_eval(d, r0, dm);
+    gh_psi = (C)psi_eval(d, rh0, dm);
+  };
+
+  const C A = (C)d.A, Gf = (C)d.G_f, inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
+  const C bfx = (C)d.body_fx, bfy = (C)d.body_fy;
+  const C k1 = (C)(1.0 / 3.0), k2 = (C)(1.0 / 12.0);
+
+  // Eq. 9 from psi of the centre (pc), its row neighbours and the rows below (m) and above (n); written as in the
+  // one-step kernel (no fused multiply-adds; exactly odd under both mirrors).
+  auto force = [&](C pc, C pcL, C pcR, C pm, C pmL, C pmR, C pn, C pnL, C pnR, C& Fx, C& Fy) {
+#pragma clang fp contract(off)
+    const C spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
+    const C spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
+    const C sux = k1 * ((pcR - pcL) * (pcR + pcL)) +
+                  k2 * ((pnR - pnL) * (pnR + pnL) + (pmR - pmL) * (pmR + pmL));
+    const C suy = k1 * ((pn - pm) * (pn + pm)) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
+    Fx = -Gf * ((C)0.5 * A * sux + ((C)1 - A) * pc * spx) + bfx;
+    Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
+  };
+
+  // step A's rows: those step B reads, g^{t+1} of rows y0 - 2 .. ylast + 2 within the fluid rows
+  const int ya0 = y0 - 2 >= 1 ? y0 - 2 : 1, ya1 = ylast + 2 <= ny - 2 ? ylast + 2 : ny - 2;
+  const bool wall_start = ya0 == 1, wall_end = ya1 == ny - 2;
+
+  C tg = (C)0, tgL = (C)0, tgR = (C)0;  // step A's top ghost row (psi with neighbours), computed up front
+  if (wall_end) {
+    C f1[9], f2[9], r1, r2, h1, h2, p1, p2, hp1, hp2, g_rho, hg;
+    bool dm;
+    produce(ny - 2, f1, r1, p1, h1, hp1, dm);
+    produce(ny - 3, f2, r2, p2, h2, hp2, dm);
+    ghostA(1, ny - 2, r1, r2, h1, h2, g_rho, tg, hg);
+    xchg(tg, hg, tgL, tgR);
+  }
+  // window: rows (b, c, a) = (y - 1, y, y + 1) when step A processes row y
+  C fc[9], fn[9], fp[9];
+  C rb, rc, ra, pb, pc, pa, pbL, pbR, pcL, pcR, paL, paR;
+  {
+    C hpb, hpc, hpa, hrb, hrc, hra;
+    bool dm;
+    if (wall_start) {
+      produce(ya0, fc, rc, pc, hrc, hpc, dm);
+      produce(ya0 + 1, fn, ra, pa, hra, hpa, dm);
+      ghostA(0, ya0, rc, ra, hrc, hra, rb, pb, hpb);
+    } else {
+      C fb[9];
+      produce(ya0 - 1, fb, rb, pb, hrb, hpb, dm);
+      produce(ya0, fc, rc, pc, hrc, hpc, dm);
+      if (ya0 + 1 <= ny - 2) produce(ya0 + 1, fn, ra, pa, hra, hpa, dm);
+    }
+    xchg(pb, hpb, pbL, pbR);
+    xchg(pc, hpc, pcL, pcR);
+    if (ya0 + 1 <= ny - 2) {
+      xchg(pa, hpa, paL, paR);
+    } else {
+      pa = tg; paL = tgL; paR = tgR;
+    }
+  }
+  // rows gathered by step A: ya0 - 1 .. ya1 + 1 within the fluid rows; the populations of row y + 2 are in flight
+  // while row y is processed
+  const int yread = ya1 + 1 <= ny - 2 ? ya1 + 1 : ny - 2;
+  if (act && ya0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ya0 + 2, fp);
+
+  // ---------------------------------------------------------------------------------------------- step B state
+  const bool wallB_bot = y0 == 1, wallB_top = ylast == ny - 2;
+  const int jb0 = y0 - 1 >= 1 ? y0 - 1 : 1, jb1 = ylast + 1 <= ny - 2 ? ylast + 1 : ny - 2;  // rows B gathers
+  C fBp[9], rBp = (C)0;  // step B's populations and density of the row gathered in the previous iteration
+  C rBtop2 = (C)0;       // density of row ny - 3 on the own lane (top ghost row of step B)
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fBp[i] = (C)0;
+
+  // Iteration y: step A collides row y; step B gathers row y - 1 and collides row y - 2.
+  const int yend = ylast + 2;
+  for (int y = ya0;; ++y) {
+    // ---- step A: collide row y into the ring, then bring row y + 2 into the window
+    bool slid = false;
+    if (y <= ya1) {
+      if (act) {
+        C Fx, Fy, fs[9];
+        force(pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, Fx, Fy);
+        collide<C, true>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
+        const int s = y % 3;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gA[s][i][lx] = fs[i];
+      }
+      if (y < ya1) {
+        rb = rc; pb = pc; pbL = pcL; pbR = pcR;
+        rc = ra; pc = pa; pcL = paL; pcR = paR;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fc[i] = fn[i];
+        const int ynew = y + 2;
+        if (ynew <= ny - 2) {
+          C g[9];
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fn[i] = act ? fp[i] : (C)0;
+          if (act && ynew + 1 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + 1, fp);
+          if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
+          bool dm;
+          ra = rho0 + sum9(fn);
+          pa = psi_eval(d, ra, dm);
+          C hpa = (C)0;
+          if (edge) hpa = psi_eval(d, rho0 + sum9(g), dm);
+          xput(pa, hpa);
+          slid = true;
+        } else {
+          pa = tg; paL = tgL; paR = tgR;
+        }
+      }
+    }
+    __syncthreads();  // step A's row y is in the ring; the psi of row y + 2 is in xa
+    if (slid) xget(paL, paR);
+
+    // ---- step B: gather row j = y - 1 from the ring (density, psi), ghost rows at the walls
+    const int j = y - 1;
+    const bool doG = j >= jb0 && j <= jb1;
+    C fg[9], rj = (C)0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fg[i] = (C)0;
+    if (doG && actBg) {
+      const bool bot = j == 1, top = j == ny - 2;
+      const int sm = (j + 2) % 3, sc = j % 3, sp = (j + 1) % 3;  // ring slots of rows j - 1, j, j + 1
+      fg[0] = gA[sc][0][lx];
+      fg[1] = gA[sc][1][lx - 1];
+      fg[2] = bot ? gA[sc][4][lx] : gA[sm][2][lx];
+      fg[3] = gA[sc][3][lx + 1];
+      fg[4] = top ? gA[sc][2][lx] : gA[sp][4][lx];
+      fg[5] = bot ? gA[sc][7][lx] : gA[sm][5][lx - 1];
+      fg[6] = bot ? gA[sc][8][lx] : gA[sm][6][lx + 1];
+      fg[7] = top ? gA[sc][5][lx] : gA[sp][7][lx + 1];
+      fg[8] = top ? gA[sc][6][lx] : gA[sp][8][lx - 1];
+      rj = rho0 + sum9(fg);
+      bool dm;
+      psB[sc][lx] = psi_eval(d, rj, dm);
+      if (bot) rhB[0][lx] = rj;
+      if (top) rhB[1][lx] = rj;
+    }
+    if (doG && j == ny - 3) rBtop2 = rj;
+    // bottom ghost row (row 0, ring slot 0) once rows 1 and 2 are in: row 1's densities through LDS
+    if (wallB_bot && doG && j == 2 && actBw) {
+      bool gc, dm;
+      const double r0 = ghost_density((double)rhB[0][lx - 1], (double)rhB[0][lx + 1], (double)rhB[0][lx],
+                                      (double)rj, cos_th[col], cot_th[col], iters, d.rho_cap_hi, gc);
+      psB[0][lx] = (C)psi_eval(d, r0, dm);
+    }
+    // top ghost row (row ny - 1) after the last gather: row ny - 2's densities through LDS, row ny - 3's own
+    if (wallB_top && y == ny && actBw) {
+      bool gc, dm;
+      const double r0 = ghost_density((double)rhB[1][lx - 1], (double)rhB[1][lx + 1], (double)rhB[1][lx],
+                                      (double)rBtop2, cos_th[nx + col], cot_th[nx + col], iters, d.rho_cap_hi, gc);
+      psB[(ny - 1) % 3][lx] = (C)psi_eval(d, r0, dm);
+    }
+    __syncthreads();  // step B's psi of row j (and a ghost row) are in the ring
+
+    // ---- step B: collide row m = y - 2 (gathered in the previous iteration) and store it
+    const int m = y - 2;
+    if (m >= y0 && m <= ylast && actBc) {
+      C Fx, Fy, fs[9];
+      const int s0 = (m + 2) % 3, s1 = m % 3, s2 = (m + 1) % 3;  // rows m - 1, m, m + 1
+      force(psB[s1][lx], psB[s1][lx - 1], psB[s1][lx + 1], psB[s0][lx], psB[s0][lx - 1], psB[s0][lx + 1],
+            psB[s2][lx], psB[s2][lx - 1], psB[s2][lx + 1], Fx, Fy);
+      collide<C, true>(fBp, rBp, rBp - rho0, Fx, Fy, inv_tau, pref, (C)1 / rBp, fs);
+      const unsigned off = (unsigned)((m - 1) * pitch + col);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ((GS*)(gout + i * plane))[off] = fs[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fBp[i] = fg[i];
+    rBp = rj;
+    if (y == yend) break;
+  }
+}
+
+template <int W>
+int occupancy_of(int* blocks) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<W>, WAVE * W, 0);
+}
+
+}  // namespace
+
+hipError_t step2_blocks_per_cu(int waves, int* blocks) {
+  *blocks = 0;
+  switch (waves) {
+    case 1: return (hipError_t)occupancy_of<1>(blocks);
+    case 2: return (hipError_t)occupancy_of<2>(blocks);
+    case 4: return (hipError_t)occupancy_of<4>(blocks);
+    default: return (hipError_t)occupancy_of<8>(blocks);
+  }
+}
+
+hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip,
+                        hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)(((ntasks + kXcds - 1) / kXcds) * kXcds);
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_step2<1>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 2: hipLaunchKernelGGL((k_step2<2>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 4: hipLaunchKernelGGL((k_step2<4>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    default: hipLaunchKernelGGL((k_step2<8>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm

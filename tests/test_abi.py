@@ -61,7 +61,7 @@ def test_workspace_bytes_and_validation():
         dict(nx=20, ny=10, T_over_Tc=0.8, tau=0.5),
         dict(nx=20, ny=10, T_over_Tc=0.8, G=1.0),
         dict(nx=20, ny=10, T_over_Tc=0.8, wet_iters=-1),
-        dict(nx=20, ny=10, T_over_Tc=0.8, step_variant=9),
+        dict(nx=20, ny=10, T_over_Tc=0.8, step_variant=13),
         dict(nx=20, ny=10, T_over_Tc=0.8, rho0_shift=0.3),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary=3),
         dict(nx=20, ny=10, T_over_Tc=0.8, boundary="martys_chen", G_w=(float("inf"), -1.0)),
