@@ -188,6 +188,17 @@ int lbm_step_timed(lbm_ctx* c, int32_t inst, int64_t nsteps, double* ms);
  * Synchronizes the stream. */
 int lbm_measure_contact_angle(lbm_ctx* c, int32_t inst, int32_t wall, const int32_t box[4], double out[5]);
 
+/* lbm_measure_contact_angle for callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the same measurement on a density field the caller holds, with no
+ * context and no workspace. d_rho: device FP64 field [ny][nx] (row 0 and ny-1 the ghost rows, as lbm_get_rho
+ * writes it), read only; box, wall and out[5] as for lbm_measure_contact_angle (results identical to it on the same
+ * field). The reduction partials live in a library-owned device array of 512 x 10 doubles (40 KiB) per GPU, held
+ * until the process ends; the measurement's grid is fixed, so any field size fits (nx >= 2, ny >= 4,
+ * nx ny <= 2^34). Nothing is allocated. Runs on the current device on hip_stream and synchronizes it. Calls that
+ * overlap on one GPU share that array and race: serialize them. */
+int lbm_measure_contact_angle_noalloc(const double* d_rho, int32_t nx, int32_t ny, int32_t wall,
+                                      const int32_t box[4], void* hip_stream, double out[5]);
+
 /* FP64 total mass (sum of all populations over fluid nodes) of the current state. Synchronizes the stream. */
 int lbm_mass(lbm_ctx* c, int32_t inst, double* out);
 

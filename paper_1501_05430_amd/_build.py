@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_step2.hip"), os.path.join(CSRC, "lbm_adjoint.hip"),
-           os.path.join(CSRC, "lbm_api.cpp")]
+           os.path.join(CSRC, "lbm_noalloc.hip"), os.path.join(CSRC, "lbm_api.cpp")]
 HEADERS = [os.path.join(CSRC, "lbm_internal.h"), os.path.join(CSRC, "lbm_device.h"),
            os.path.join(os.path.dirname(HERE), "include", "lbm.h")]
 # bandwidth probes used by bench.py for the copy ceiling (not part of the method's library)

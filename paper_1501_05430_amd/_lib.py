@@ -69,6 +69,8 @@ _SIGS = {
     "lbm_adjoint_seed_rho": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_adjoint_seed_rho_f32": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p]),
+    "lbm_measure_contact_angle_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                                    C.POINTER(C.c_int32), C.c_void_p, C.POINTER(C.c_double)]),
     "lbm_last_error": (C.c_char_p, []),
 }
 
