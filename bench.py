@@ -43,14 +43,15 @@ def kernel_sha():
 
 
 def profile_traffic(path):
-    """HBM bytes per launch from a committed counter summary, if it was taken on the current step sources."""
+    """(HBM bytes per launch, time steps per launch) from a committed counter summary, if it was taken on the current
+    sources of the kernel; (None, 1) otherwise."""
     if not os.path.exists(path):
-        return None
+        return None, 1
     with open(path) as f:
         tr = json.load(f)
     if tr.get("kernel_source_sha256") != kernel_sha():
-        return None
-    return tr.get("hbm_bytes_per_launch")
+        return None, 1
+    return tr.get("hbm_bytes_per_launch"), tr.get("time_steps_per_launch", 1)
 
 
 def make_sim(case, precision, check_every=100, **kw):
@@ -229,7 +230,8 @@ def batched_vs_plain(steps_batched=1000, steps_plain=200):
         "batched_gbs_alg": round(ach, 1),
         # the batched launches (all instances in each) against the HBM peak: 72 B per fluid node and step
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": profile_traffic(TRAFFIC_FILE_C4)},
+                     "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": profile_traffic(TRAFFIC_FILE_C4)[0],
+                     "launch": "k_step2 (two time steps per launch, every instance in each)"},
     }
     if steps_plain <= 0:
         return out
@@ -352,7 +354,7 @@ def main():
     bytes_alg = 72 * nodes  # 9 FP32 populations read + 9 written per fluid node and step
     achieved = bytes_alg / (ms_step * 1e-3) / 1e9
 
-    traffic = profile_traffic(TRAFFIC_FILE)
+    traffic, per_launch = profile_traffic(TRAFFIC_FILE)
 
     out = {
         "metric": "MLUPS & % HBM roofline; FP32/batched/adjoint vs plain FP64 at stated error",
@@ -376,8 +378,10 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            # HBM bytes of the counters (when current) over this run's time per step
-            "traffic_gbs": round(traffic / (ms_step * 1e-3) / 1e9, 1) if traffic else None,
+            # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
+            # current), traffic_gbs those bytes over this run's time per launch
+            "kernel": "k_step2 (two time steps per launch)", "steps_per_launch": 2,
+            "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic
             "copy_gbs_on_this_gpu": ceilings["copy_float4_gbs"],
