@@ -42,13 +42,14 @@ __device__ inline double dp_drho(const InstDesc& d, double rho) {
   // Carnahan-Starling: R T (1 + 4e + 4e^2 - 4e^3 + e^4)/(1 - e)^4 - 2 a rho, e = b rho / 4
   const double e = d.eos_b4 * rho, om = 1.0 - e;
   const double om2 = om * om;
-  return d.RT * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (om2 * om2) - 2.0 * d.eos_a * rho;
+  return d.RT * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) * rcp64(om2 * om2) - 2.0 * d.eos_a * rho;
 }
 
-// d psi / d rho where psi > 0 (Eq. 10): (p'(rho) - 1/3) / (G_psi psi); 0 where psi was clamped.
+// d psi / d rho where psi > 0 (Eq. 10): (p'(rho) - 1/3) / (G_psi psi); 0 where psi was clamped. The reciprocals are
+// the hardware's refined by Newton steps (about 1 ulp): a derivative needs no correctly rounded division.
 __device__ inline double dpsi_drho(const InstDesc& d, double rho, double psi) {
   if (!(psi > 0.0)) return 0.0;
-  return (dp_drho(d, rho) - 1.0 / 3.0) * (0.5 * d.two_over_Gpsi) / psi;
+  return (dp_drho(d, rho) - 1.0 / 3.0) * (0.5 * d.two_over_Gpsi) * rcp64(psi);
 }
 
 struct Field {
@@ -134,37 +135,41 @@ __global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ 
 //    direct part of lambda_n (lam) and F_bar.
 __device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fx,
                                    double Fy, double (&lam)[9], double& Fbx, double& Fby) {
-  // forward collision quantities
+  // forward collision quantities (v with the reciprocal of rho, as the forward collision forms it)
   const double rho = sum9(fl);
   const double jx = mom_x(fl), jy = mom_y(fl);
-  const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
+  const double irho = 1.0 / rho;
+  const double vx = (jx + 0.5 * Fx) * irho, vy = (jy + 0.5 * Fy) * irho;
   const double v2 = vx * vx + vy * vy;
   const double it = d.inv_tau, pref = d.force_pref;
-  double rhob = 0.0, vbx = 0.0, vby = 0.0;
-  Fbx = 0.0;
-  Fby = 0.0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const double ex = kEX[i], ey = kEY[i], w = kW[i];
-    const double eu = ex * vx + ey * vy, eF = ex * Fx + ey * Fy;
-    lam[i] = (1.0 - it) * ls[i];
-    const double q = ls[i] * it;  // adjoint of f_eq_i
-    rhob += q * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2);
-    vbx += q * w * rho * (3.0 * ex + 9.0 * eu * ex - 3.0 * vx);
-    vby += q * w * rho * (3.0 * ey + 9.0 * eu * ey - 3.0 * vy);
-    const double s = ls[i] * pref * w;  // adjoint of the forcing term / (pref w)
-    vbx += s * (-3.0 * Fx + 9.0 * eF * ex);
-    vby += s * (-3.0 * Fy + 9.0 * eF * ey);
-    Fbx += s * (3.0 * ex - 3.0 * vx + 9.0 * eu * ex);
-    Fby += s * (3.0 * ey - 3.0 * vy + 9.0 * eu * ey);
-  }
+  // Every sum over directions below is a weighted moment of the cotangent ls: with m = sum_i w_i ls_i (1, e_x, e_y,
+  // e_x^2, e_x e_y, e_y^2),
+  //   adjoint of f_eq (weight it):   rho_bar = it [m0 (1 - 1.5 v^2) + 3 v.m1 + 4.5 v.m2.v],
+  //                                  v_bar  += it rho [3 m1 + 9 m2.v - 3 v m0],
+  //   adjoint of the forcing (pref): v_bar  += pref [9 m2.F - 3 F m0],   F_bar = pref [3 m1 - 3 v m0 + 9 m2.v].
+  const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+  const double d5 = ls[5] + ls[7], d6 = ls[6] + ls[8];   // diagonal pairs
+  const double dg = d5 + d6;
+  const double m0 = w0 * ls[0] + w1 * ((ls[1] + ls[3]) + (ls[2] + ls[4])) + w2 * dg;
+  const double mx = w1 * (ls[1] - ls[3]) + w2 * ((ls[5] - ls[7]) + (ls[8] - ls[6]));
+  const double my = w1 * (ls[2] - ls[4]) + w2 * ((ls[5] - ls[7]) + (ls[6] - ls[8]));
+  const double mxx = w1 * (ls[1] + ls[3]) + w2 * dg;
+  const double myy = w1 * (ls[2] + ls[4]) + w2 * dg;
+  const double mxy = w2 * (d5 - d6);
+  const double m2vx = mxx * vx + mxy * vy, m2vy = mxy * vx + myy * vy;  // m2 . v
+  double rhob = it * (m0 * (1.0 - 1.5 * v2) + 3.0 * (vx * mx + vy * my) + 4.5 * (vx * m2vx + vy * m2vy));
+  double vbx = it * rho * (3.0 * mx + 9.0 * m2vx - 3.0 * vx * m0) + pref * (9.0 * (mxx * Fx + mxy * Fy) - 3.0 * Fx * m0);
+  double vby = it * rho * (3.0 * my + 9.0 * m2vy - 3.0 * vy * m0) + pref * (9.0 * (mxy * Fx + myy * Fy) - 3.0 * Fy * m0);
+  Fbx = pref * (3.0 * mx - 3.0 * vx * m0 + 9.0 * m2vx);
+  Fby = pref * (3.0 * my - 3.0 * vy * m0 + 9.0 * m2vy);
   // v = (j + F/2) / rho
-  const double jbx = vbx / rho, jby = vby / rho;
-  Fbx += 0.5 * vbx / rho;
-  Fby += 0.5 * vby / rho;
-  rhob -= (vbx * vx + vby * vy) / rho;
+  const double jbx = vbx * irho, jby = vby * irho;
+  Fbx += 0.5 * jbx;
+  Fby += 0.5 * jby;
+  rhob -= (jbx * vx + jby * vy);
+  const double keep = 1.0 - it;  // the relaxed part f - (f - f_eq)/tau keeps (1 - 1/tau) of ls
 #pragma unroll
-  for (int i = 0; i < 9; ++i) lam[i] += rhob + jbx * kEX[i] + jby * kEY[i];
+  for (int i = 0; i < 9; ++i) lam[i] = keep * ls[i] + rhob + jbx * kEX[i] + jby * kEY[i];
 }
 
 // D2Q9 moment basis in the order of Eq. 4 (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) and its row norms.
