@@ -322,6 +322,8 @@ def main():
                     help="autotune the step kernel's block shape first (default: the library's defaults)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 256-instance batched leg and print its JSON (for profiling that launch)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint legs on the headline lattice and print their JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the method on a single MI355X "
@@ -336,6 +338,11 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched_256": batched_vs_plain(steps_batched=args.steps, steps_plain=0)}), flush=True)
+        return
+    if args.adjoint_only:
+        case = W.c3_large()
+        print(json.dumps({"adjoint_fp64_same_lattice": adjoint_rate(case),
+                          "adjoint_fp32_storage_same_lattice": adjoint_rate(case, dtype="f32")}), flush=True)
         return
 
     case = W.c3_large()

@@ -118,6 +118,38 @@ def test_c2_fp32_full_run_vs_fp64(c2_fp64, deg, mode):
     assert max(errs) <= LONG32[mode[1]], errs
 
 
+def test_c4_sampled_fp32_instances_vs_reference():
+    """The 256-instance batch in FP32 shifted by rho_v (FP64 EOS below sqrt(rho_v rho_l)), all instances in each
+    launch (two steps per launch), 100 steps: 8 instances drawn with the seed, each against the FP64 reference over
+    its own lattice, max |drho| / rho_l <= 1e-5 (the vapour-relative error is printed)."""
+    import paper_1501_05430_amd as P
+    cases = W.c4_batch()
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision="f32_shifted",
+                            **P.fp32_options(c.T_over_Tc, "f32_shifted")) for c in cases]
+    batch = P.LBM(params)
+    for i, c in enumerate(cases):
+        batch.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
+        batch.init_droplet(c.xc, c.yc, c.R, inst=i)
+    batch.step(100, inst=-1)
+    pick = sorted(np.random.default_rng(W.SEED).choice(len(cases), 8, replace=False).tolist())
+    worst = 0.0
+    for i in pick:
+        c = cases[i]
+        ref = oracle_sim(c)
+        ref.run(100)
+        rv, rl = ref.coexistence()
+        r_ref = ref.density()[0][1:-1]
+        r = batch.rho(inst=i)[1:-1]
+        err = float(np.abs(r - r_ref).max() / rl)
+        vap = r_ref < math.sqrt(rv * rl)
+        evap = float((np.abs(r - r_ref)[vap] / r_ref[vap]).max())
+        print(f"\n  c4 instance {i} ({c.nx}x{c.ny}, T/T_c {c.T_over_Tc:.3f}, theta {math.degrees(c.theta_bottom[0]):.1f}):"
+              f" max|drho|/rho_l {err:.2e}, vapour max|drho|/rho {evap:.2e}")
+        worst = max(worst, err)
+    batch.close()
+    assert worst <= TOL32, worst
+
+
 @pytest.fixture(scope="module")
 def c3_reference():
     case = W.c3_large()
@@ -188,9 +220,9 @@ def test_free_droplet_stays_mirror_symmetric_bitwise(precision):
 @pytest.mark.parametrize("deg", [60, 90, 120])
 def test_c2_measured_angle_settles_near_prescribed(deg):
     """The whole scheme against its own target: after 100 000 steps (FP64, settled to 0.01 deg between 100k and
-    300k steps) the fitted contact angle is within 3 deg of the prescribed one. (30 deg settles at 33.0 deg, and a
-    150 deg droplet keeps oscillating between about 146 and 160 deg at this resolution; both are reported, not
-    tested.)"""
+    300k steps) the fitted contact angle is within 3 deg of the prescribed one. (30 deg settles at 33.0 deg: see
+    the next test; a 150 deg droplet keeps oscillating between about 146 and 160 deg at this resolution, reported,
+    not tested.)"""
     case = W.c2_angle(deg)
     sim = gpu_sim(case, precision="f64", check_every=10000)
     sim.step(100000)
@@ -200,6 +232,26 @@ def test_c2_measured_angle_settles_near_prescribed(deg):
     print(f"\n  c2 theta={deg}: measured {th:.2f} deg after 100 000 steps")
     assert d["nonfinite"] == 0 and d["ghost_clamps"] == 0
     assert abs(th - deg) <= 3.0, th
+
+
+def test_c2_thirty_degrees_offset_does_not_depend_on_resolution():
+    """The 1024 x 512 workload's physics at 30 deg settles 3.0 deg high, and the same at half and double the droplet
+    radius (measured 33.03 / 33.01 / 33.03 deg at R = 60 / 120 / 240 with the cap start): a fixed offset of the scheme
+    with this EOS and temperature, not a discretisation error that refinement would remove. Checked at R = 60 and 120
+    (the R = 240 run takes 20 s), each within 3.1 deg of 30 and within 0.1 deg of each other."""
+    import paper_1501_05430_amd as P
+    th = {}
+    for R, nx, ny, steps in ((60.0, 512, 256, 35355), (120.0, 1024, 512, 100000)):
+        t = math.radians(30.0)
+        sim = P.LBM(P.make_params(nx, ny, 0.7, check_every=5000))
+        sim.apply_wetting(t, math.pi / 2)
+        sim.init_droplet(nx / 2, W.wall_cap_centre(R, t), R)
+        sim.step(steps)
+        th[R] = math.degrees(sim.measure_contact_angle((0, nx, 1, ny - 20), 0)[0])
+        sim.close()
+    print(f"\n  30 deg at T = 0.7 T_c: R = 60 -> {th[60.0]:.2f}, R = 120 -> {th[120.0]:.2f} deg")
+    assert abs(th[60.0] - th[120.0]) <= 0.1, th
+    assert all(abs(v - 30.0) <= 3.1 for v in th.values()), th
 
 
 @pytest.mark.parametrize("ratio", [100, 1000])
