@@ -70,13 +70,49 @@ __device__ inline double block_sum(double v, double* sm) {
   return t;
 }
 
-// 1. forward density and psi of a fluid node from its populations (summed in index order; every pass uses this)
+// psi of Eq. 10 at one density and its derivative dpsi/drho (0 where the argument is clamped at 0: the
+// sub-gradient at the kink). The division and the square root are the hardware's reciprocal and reciprocal square
+// root refined by Newton / Goldschmidt steps (about 1 ulp): the reverse pass linearises about these values and does
+// not have to reproduce the forward step's rounding.
+__device__ inline void psi_dpsi(const InstDesc& d, double rho, double& psi, double& dps) {
+  double p, dp;
+  if (d.eos_kind == 1) {  // Eq. 11, the segment chosen by the forward step's comparisons
+    if (rho <= d.pw_r1) {
+      p = rho * d.pw_t[0];
+      dp = d.pw_t[0];
+    } else if (rho <= d.pw_r2) {
+      p = d.pw_p1 + (rho - d.pw_r1) * d.pw_t[1];
+      dp = d.pw_t[1];
+    } else {
+      p = d.pw_p2 + (rho - d.pw_r2) * d.pw_t[2];
+      dp = d.pw_t[2];
+    }
+  } else {  // Carnahan-Starling, e = b rho / 4: p' = R T (1 + 4e + 4e^2 - 4e^3 + e^4)/(1 - e)^4 - 2 a rho
+    const double e = d.eos_b4 * rho, io = rcp64(1.0 - e), io3 = io * io * io;
+    p = rho * d.RT * (1.0 + e + e * e - e * e * e) * io3 - d.eos_a * rho * rho;
+    dp = d.RT * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) * (io3 * io) - 2.0 * d.eos_a * rho;
+  }
+  const double arg = d.two_over_Gpsi * (p - rho * (1.0 / 3.0));
+  if (arg <= 0.0) {
+    psi = 0.0;
+    dps = 0.0;
+    return;
+  }
+  // s -> sqrt(arg), h -> 1 / (2 sqrt(arg))
+  const double y = __builtin_amdgcn_rsq(arg);
+  double s = arg * y, h = 0.5 * y;
+  const double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  psi = fma(fma(-s, s, arg), h, s);
+  dps = (dp - 1.0 / 3.0) * d.two_over_Gpsi * h;  // (p' - 1/3) (2 / G_psi) / (2 psi)
+}
+
+// 1. forward density and psi of a fluid node from its populations (every pass of the reverse step uses these)
 __device__ inline void node_rho_psi(const InstDesc& d, const double (&fl)[9], double& r, double& p) {
-  r = fl[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) r += fl[i];
-  bool cl;
-  p = psi_f64(d, r, cl);
+  r = sum9(fl);
+  double dps;
+  psi_dpsi(d, r, p, dps);
 }
 
 template <class T>
@@ -131,14 +167,13 @@ __global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ 
   sc.gflag[wall * nx + c] = cl ? 1.0 : 0.0;
 }
 
-// 2. streaming and collision transposed at a fluid node, BGK: given lambda* (ls) and the node's total force F, the
-//    direct part of lambda_n (lam) and F_bar.
-__device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fx,
-                                   double Fy, double (&lam)[9], double& Fbx, double& Fby) {
-  // forward collision quantities (v with the reciprocal of rho, as the forward collision forms it)
-  const double rho = sum9(fl);
-  const double jx = mom_x(fl), jy = mom_y(fl);
-  const double irho = 1.0 / rho;
+// 2. streaming and collision transposed at a fluid node, BGK: given lambda* (ls), the node's forward density and
+//    momentum and its total force F: F_bar and the direct part of lambda_n,
+//    lam_i = (1 - 1/tau) ls_i + h + hx e_ix + hy e_iy.
+__device__ inline void collide_adj(const InstDesc& d, double rho, double jx, double jy, const double (&ls)[9],
+                                   double Fx, double Fy, double& h, double& hx, double& hy, double& Fbx,
+                                   double& Fby) {
+  const double irho = rcp64(rho);
   const double vx = (jx + 0.5 * Fx) * irho, vy = (jy + 0.5 * Fy) * irho;
   const double v2 = vx * vx + vy * vy;
   const double it = d.inv_tau, pref = d.force_pref;
@@ -167,9 +202,9 @@ __device__ inline void collide_adj(const InstDesc& d, const double (&fl)[9], con
   Fbx += 0.5 * jbx;
   Fby += 0.5 * jby;
   rhob -= (jbx * vx + jby * vy);
-  const double keep = 1.0 - it;  // the relaxed part f - (f - f_eq)/tau keeps (1 - 1/tau) of ls
-#pragma unroll
-  for (int i = 0; i < 9; ++i) lam[i] = keep * ls[i] + rhob + jbx * kEX[i] + jby * kEY[i];
+  h = rhob;
+  hx = jbx;
+  hy = jby;
 }
 
 // D2Q9 moment basis in the order of Eq. 4 (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) and its row norms.
@@ -183,10 +218,11 @@ constexpr double kMomNorm[9] = {9.0, 36.0, 36.0, 6.0, 12.0, 6.0, 12.0, 4.0, 4.0}
 //     + (1 - s_k/2) S_k + C_k on the non-conserved moments and dm = F on j. Reverse: dm_bar = D^-1 M lambda*, then
 //     the relaxation (through m = M f), the equilibria and forcing moments (through rho and v = (j + F/2)/rho) and
 //     the source (Q_bar, the adjoint of Q of Eq. 17, xx / yy / xy).
-__device__ inline void collide_mrt_adj(const InstDesc& d, const double (&fl)[9], const double (&ls)[9], double Fx,
-                                       double Fy, double (&lam)[9], double& Fbx, double& Fby, double (&qb)[3]) {
-  const double rho = sum9(fl), jx = mom_x(fl), jy = mom_y(fl);
-  const double vx = (jx + 0.5 * Fx) / rho, vy = (jy + 0.5 * Fy) / rho;
+__device__ inline void collide_mrt_adj(const InstDesc& d, double rho, double jx, double jy, const double (&ls)[9],
+                                       double Fx, double Fy, double (&lam)[9], double& Fbx, double& Fby,
+                                       double (&qb)[3]) {
+  const double irho = rcp64(rho);
+  const double vx = (jx + 0.5 * Fx) * irho, vy = (jy + 0.5 * Fy) * irho;
   const double v2 = vx * vx + vy * vy;
   const double sn = d.inv_tau;
   double dmb[9];
@@ -216,10 +252,10 @@ __device__ inline void collide_mrt_adj(const InstDesc& d, const double (&fl)[9],
   qb[1] = 1.5 * d.s_e * dmb[1] + sn * dmb[7];
   qb[2] = -sn * dmb[8];
   // v = (j + F/2) / rho
-  const double jbx = vbx / rho, jby = vby / rho;
-  Fbx += 0.5 * vbx / rho;
-  Fby += 0.5 * vby / rho;
-  rhob -= (vbx * vx + vby * vy) / rho;
+  const double jbx = vbx * irho, jby = vby * irho;
+  Fbx += 0.5 * jbx;
+  Fby += 0.5 * jby;
+  rhob -= (jbx * vx + jby * vy);
   const double mr[9] = {0.0, -a1, -a2, 0.0, -a4, 0.0, -a6, -a7, -a8};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -321,14 +357,15 @@ __global__ __launch_bounds__(AB) void ka_ghost_adj(const InstDesc* __restrict__ 
 
 // 3 + 5 fused: one wavefront walks a strip of rows [y0, ylast] over at most 60 columns. Row by row it transposes
 // the streaming and collision one row ahead (stage C, also on one halo column at each side and on the rows y0 - 1
-// and ylast + 1; a second halo column at each side only supplies psi), keeps that row's F_bar in a ring of three rows in LDS, and transposes the force and psi for the
-// row behind (stage S): psi_bar from its own force and the eight neighbours' forces, rho_bar = psi_bar dpsi/drho,
-// and lambda_n = direct part + rho_bar, written once. Density and psi are computed here from the populations,
-// which are loaded two rows ahead of stage C and kept until it uses them; psi and rho live in a window of rows in
-// registers (neighbour columns by lane shuffles; the ghost rows' psi from the scratch field). Every global load of a row iteration is for a later row, in flight while the current
-// rows are computed. F_bar of the boundary rows 1 and ny-2 also goes to the scratch for the ghost rows' adjoint,
-// whose boundary-row terms ka_wall_fix adds afterwards. Partials of G_f_bar (stage C) and G_psi_bar (stage S) per
-// block, over the block's own columns and rows only.
+// and ylast + 1; a second halo column at each side only supplies psi), keeps that row's F_bar in a ring of three
+// rows in LDS, and transposes the force and psi for the row behind (stage S): psi_bar from its own force and the
+// eight neighbours' forces, rho_bar = psi_bar dpsi/drho, and lambda_n = direct part + rho_bar, written once.
+// Per row the window keeps the forward values the two stages read (psi with its left and right neighbours,
+// dpsi/drho, density and momentum), computed once from the row's populations; the populations are loaded two rows
+// ahead of stage C and lambda* one row ahead, so every global load of a row iteration is for a later row. The
+// ghost rows' psi comes from the scratch field. F_bar of the boundary rows 1 and ny-2 also goes to the scratch for
+// the ghost rows' adjoint, whose boundary-row terms ka_wall_fix adds afterwards. Partials of G_f_bar (stage C) and
+// G_psi_bar (stage S) per block, over the block's own columns and rows only.
 constexpr int FL = 64;         // lanes per block (one wavefront): at most 60 own columns, two halo columns each side
 
 // Interaction force (Eq. 9) from the 3 x 3 psi values around the node: rows below (m), own (c), above (n).
@@ -343,6 +380,16 @@ __device__ inline void force_vals(const InstDesc& d, double pmL, double pm, doub
   Fy = -Gf * (0.5 * A * suy + (1.0 - A) * pc * spy);
 }
 
+// Left and right neighbours of a per-lane value across the wavefront: lane l receives the values of lanes l - 1
+// and l + 1 (wavefront shifts by one lane, both 32-bit halves; lanes 0 and 63 receive their own value).
+__device__ inline void lane_lr(double v, double& L, double& R) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  L = __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),   // wave_shr:1
+                       __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+  R = __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),   // wave_shl:1
+                       __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
 // EXT: the MRT collision with the source of Eq. 16-17 (Q_bar joins F_bar in the ring) and the fluid-solid force of
 // Eq. 14 on the boundary rows; without it only the BGK collision with geometric walls is compiled.
 // T: storage type of the state and of lambda (double, or float for lbm_adjoint_step_f32); the arithmetic is FP64.
@@ -352,8 +399,9 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
                                                   T* __restrict__ lam0, AdjScratch sc, int bw, int ncb, int H,
                                                   int ntasks) {
   constexpr int NR = EXT ? 5 : 2;  // per node in the ring: F_bar (x, y), then Q_bar (xx, yy, xy)
+  constexpr int ND = EXT ? 9 : 1;  // EXT: the direct part of lambda_n of two rows, written by C and read by S
   __shared__ double ring[3][NR][FL];
-  __shared__ double ldir[9][FL];  // direct part of lambda_n of the stage C row, read back by the next stage S
+  __shared__ double ldir[2][ND][FL];
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int64_t n = (int64_t)nx * (ny - 2);
@@ -364,204 +412,231 @@ __global__ __launch_bounds__(FL, 2) void ka_fused(const InstDesc* __restrict__ d
   const bool py = d.periodic_y != 0;  // periodic rows: rows are walked as virtual rows, wrapped to 1 .. ny-2
   auto wy = [&](int y) { return y < 1 ? y + (ny - 2) : (y > ny - 2 ? y - (ny - 2) : y); };
   const double kq = mrt ? d.kq : 0.0, gwb = d.gw_half[0], gwt = d.gw_half[1];
+  const double keep = 1.0 - d.inv_tau;  // BGK: the relaxed part f - (f - f_eq)/tau keeps (1 - 1/tau) of lambda*
+  const bool kept = keep != 0.0;
   double gf_part = 0.0, gpsi = 0.0;
-  for (int t = (int)blockIdx.x; t < ntasks; t += (int)gridDim.x) {
+  // XCD-aware order: blocks go round-robin to the eight XCDs (the grid is a multiple of 8); XCD k takes the k-th
+  // contiguous share of the task slots, so neighbouring column blocks of a strip, which read the same cache lines
+  // at their common edge, share one L2
+  const int nslots = (ntasks + 7) / 8 * 8, per = nslots / 8;
+  for (int i = (int)blockIdx.x; i < nslots; i += (int)gridDim.x) {
+    const int t = (i % 8) * per + i / 8;
+    if (t >= ntasks) continue;  // uniform over the block
     const int cb = t % ncb, sb = t / ncb;
     const int x0 = cb * bw, w = min(bw, nx - x0);
     const int y0 = 1 + sb * H, ylast = min(ny - 2, y0 + H - 1);
     // lanes 0 .. w+3: columns x0-2 .. x0+w+1 (one period at most: nx >= 2); stage C is valid on lanes 1 .. w+2
-    // (lanes 0 and w+3 only supply psi), stage S runs on the block's own columns, lanes 2 .. w+1
-    const bool act = l <= w + 3;
+    // (lanes 0 and w+3 only supply psi), stage S runs on the block's own columns, lanes 2 .. w+1. The lanes past
+    // w+3 repeat column x0 and their results are not used.
     const bool own = l >= 2 && l <= w + 1;
-    const int x = act ? wrapx(x0 - 2 + l, nx) : 0;
+    const int x = l <= w + 3 ? wrapx(x0 - 2 + l, nx) : x0;
+    const int xl = wrapx(x - 1, nx), xr = wrapx(x + 1, nx);
     const int yc0 = py ? y0 - 1 : max(1, y0 - 1), yc1 = py ? ylast + 1 : min(ny - 2, ylast + 1);
     auto fluid = [&](int y) { return py || (y >= 1 && y <= ny - 2); };
-    // loads keep the storage type: a prefetched row is widened only where the window slides, so nothing waits
-    // for it earlier (a conversion right after the load would)
+    auto rowk = [&](int y) { return (unsigned)((wy(y) - 1) * nx); };  // node counts are below 2^31
+    // populations of the node in row y: loads keep the storage type and are widened where the row is used
     auto load_f = [&](int y, T (&fl)[9]) {
-      const unsigned k = (unsigned)((wy(y) - 1) * nx + x);
+      const unsigned k = rowk(y) + (unsigned)x;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fl[i] = act ? f[i * n + k] : (T)0;
+      for (int i = 0; i < 9; ++i) fl[i] = f[i * n + k];
     };
-    auto widen = [&](const T (&a)[9], double (&b)[9]) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) b[i] = (double)a[i];
-    };
+    // 1. lambda*_i(x) = lambda_i(x + e_i), or lambda_opp(i)(x) where x + e_i is a wall row (bounce-back)
     auto load_lam = [&](int y, T (&ls)[9]) {
-      const int yw = wy(y);
-      const unsigned k = (unsigned)((yw - 1) * nx + x);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        int yd = yw + kEY[i];
-        const bool wall = !py && (yd < 1 || yd > ny - 2);
-        if (py) yd = wy(yd);
-        ls[i] = !act ? (T)0
-                     : (wall ? lam1[kOPP[i] * n + k] : lam1[i * n + (unsigned)((yd - 1) * nx + wrapx(x + kEX[i], nx))]);
-      }
+      const bool bot = !py && y == 1, top = !py && y == ny - 2;
+      const unsigned r0 = rowk(y), rd = bot ? r0 : rowk(y - 1), ru = top ? r0 : rowk(y + 1);
+      const unsigned xo = r0 + (unsigned)x;
+      auto L = [&](int q, unsigned off) -> T { return lam1[q * n + off]; };
+      ls[0] = L(0, xo);
+      ls[1] = L(1, r0 + (unsigned)xr);
+      ls[3] = L(3, r0 + (unsigned)xl);
+      ls[2] = L(top ? 4 : 2, top ? xo : ru + (unsigned)x);
+      ls[5] = L(top ? 7 : 5, top ? xo : ru + (unsigned)xr);
+      ls[6] = L(top ? 8 : 6, top ? xo : ru + (unsigned)xl);
+      ls[4] = L(bot ? 2 : 4, bot ? xo : rd + (unsigned)x);
+      ls[7] = L(bot ? 5 : 7, bot ? xo : rd + (unsigned)xl);
+      ls[8] = L(bot ? 6 : 8, bot ? xo : rd + (unsigned)xr);
     };
-    // window at the stage C row yc: psi of rows yc-2 (a), yc-1 (b), yc (c), yc+1 (e), rho of rows yc-1 (rb),
-    // yc (rc), yc+1 (re); populations of rows yc (fA), yc+1 (fB); pg the ghost row's psi when row yc+1 is one
-    double pa = 0.0, pb = 0.0, pc = 0.0, pe = 0.0, rb = 0.0, rc = 0.0, re = 0.0, pg = 0.0;
-    double fA[9], fB[9], lsA[9], lcur[9];
-    T fN[9], lsN[9], tt[9];  // fN, lsN: the prefetched row, in the storage type
+    auto node = [&](const T (&fl)[9], double& r, double& jx, double& jy, double& p, double& dp) {
+      double v[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      fB[i] = lcur[i] = 0.0;
-      fN[i] = lsN[i] = (T)0;
-    }
+      for (int i = 0; i < 9; ++i) v[i] = (double)fl[i];
+      r = sum9(v);
+      jx = mom_x(v);
+      jy = mom_y(v);
+      psi_dpsi(d, r, p, dp);
+    };
+    // window at the stage C row yc: psi (own, left, right) of rows yc-2 (a), yc-1 (b), yc (c); dpsi/drho of rows
+    // b and c; density and momentum of row c; the direct part of lambda_n of row b (BGK: h + hx e_x + hy e_y, and
+    // lambda* of row b where 1/tau != 1); the populations of row yc+1 (fN) and lambda* of row yc (lsA)
+    double pa = 0.0, aL = 0.0, aR = 0.0, pb = 0.0, bL = 0.0, bR = 0.0, pc = 0.0, cL = 0.0, cR = 0.0;
+    double db = 0.0, dc = 0.0, rc = 0.0, jxc = 0.0, jyc = 0.0, pg = 0.0, hb = 0.0, hbx = 0.0, hby = 0.0;
+    T fN[9], lsA[9], lsN[9], lsB[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lsN[i] = lsB[i] = (T)0;
     if (fluid(yc0 - 1)) {
-      double ft[9];
-      load_f(yc0 - 1, tt);
-      widen(tt, ft);
-      node_rho_psi(d, ft, rb, pb);
+      double r, jx, jy;
+      load_f(yc0 - 1, fN);
+      node(fN, r, jx, jy, pb, db);
     } else {
-      pb = act ? P.at(x, yc0 - 1) : 0.0;  // ghost row
+      pb = P.at(x, yc0 - 1);  // ghost row
     }
-    load_f(yc0, tt);
-    widen(tt, fA);
-    node_rho_psi(d, fA, rc, pc);
-    if (fluid(yc0 + 1)) {
-      load_f(yc0 + 1, tt);
-      widen(tt, fB);
-    } else {
-      pg = act ? P.at(x, yc0 + 1) : 0.0;
-    }
-    load_lam(yc0, tt);
-    widen(tt, lsA);
-    // left / right neighbours of a per-lane value (meaningful on lanes 1 .. w+2)
-    auto lr = [&](double v, double& L, double& Rr) {
-      L = __shfl(v, l > 0 ? l - 1 : 0, FL);
-      Rr = __shfl(v, l < FL - 1 ? l + 1 : FL - 1, FL);
-    };
-    auto stage_s = [&](int ys, double aL, double aR, double bL, double bR, double cL, double cR) {
-      // psi rows ys-1 (a), ys (b), ys+1 (c); rho of row ys in rb
+    lane_lr(pb, bL, bR);
+    load_f(yc0, fN);
+    node(fN, rc, jxc, jyc, pc, dc);
+    lane_lr(pc, cL, cR);
+    if (fluid(yc0 + 1)) load_f(yc0 + 1, fN);
+    else pg = P.at(x, yc0 + 1);
+    load_lam(yc0, lsA);
+    // stage S at row ys: psi rows ys-1 (a), ys (b), ys+1 (c), dpsi/drho of row ys in db
+    auto stage_s = [&](int ys) {
+      const double* Ra = &ring[(ys - 1) % 3][0][0];
+      const double* Rb = &ring[ys % 3][0][0];
+      const double* Rc = &ring[(ys + 1) % 3][0][0];
       const double pv[3][3] = {{aL, pa, aR}, {bL, pb, bR}, {cL, pc, cR}};  // [row ys-1..ys+1][x-1..x+1]
       const double spx = k1 * (bR - bL) + k2 * ((cR - cL) + (aR - aL));
       const double spy = k1 * (pc - pa) + k2 * ((cR + cL) - (aR + aL));
-      double acc = -Gf * (1.0 - A) * (ring[ys % 3][0][l] * spx + ring[ys % 3][1][l] * spy);
+      double acc = -Gf * (1.0 - A) * (Rb[l] * spx + Rb[FL + l] * spy);
       if constexpr (EXT) {
         // fluid-solid force of Eq. 14 on the boundary rows: F_s,y = +-(G_w / 2) psi
-        if (mcw && ys == 1) acc += gwb * ring[ys % 3][1][l];
-        if (mcw && ys == ny - 2) acc -= gwt * ring[ys % 3][1][l];
+        if (mcw && ys == 1) acc += gwb * Rb[FL + l];
+        if (mcw && ys == ny - 2) acc -= gwt * Rb[FL + l];
         if (kq != 0.0) {
           // own Q (Eq. 17): d Q / d psi(x) = kq [(1 - A) a - psi W], a = sum_a w_a (psi_a - psi) e_a e_a, W = I
           const double dg = ((cR + cL) + (aR + aL)) - 4.0 * pb;
           const double axx = k1 * ((bR + bL) - 2.0 * pb) + k2 * dg;
           const double ayy = k1 * ((pc + pa) - 2.0 * pb) + k2 * dg;
           const double axy = k2 * ((cR - cL) - (aR - aL));
-          const double* qo = &ring[ys % 3][2][0];
-          const double qxx = qo[l], qyy = qo[FL + l], qxy = qo[2 * FL + l];
+          const double qxx = Rb[2 * FL + l], qyy = Rb[3 * FL + l], qxy = Rb[4 * FL + l];
           acc += kq * ((1.0 - A) * (qxx * axx + qyy * ayy + qxy * axy) - pb * (qxx + qyy));
         }
       }
+      // the neighbour x = y - e_q lies in row ys - e_qy: rows below (e_qy = 1) and above (e_qy = -1) are skipped
+      // where they are wall rows
+      const bool lo_ok = py || ys > 1, hi_ok = py || ys < ny - 2;
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
-        const int yn = ys - kEY[q];
-        if (!py && (yn < 1 || yn > ny - 2)) continue;
-        const int ln = l - kEX[q], slot = yn % 3;
+        if ((kEY[q] == 1 && !lo_ok) || (kEY[q] == -1 && !hi_ok)) continue;
+        const double* Rq = kEY[q] == 1 ? Ra : (kEY[q] == 0 ? Rb : Rc);
+        const int ln = l - kEX[q];
         const double wa = q < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
-        double fe = -Gf * (ring[slot][0][ln] * kEX[q] + ring[slot][1][ln] * kEY[q]);
+        double fe = -Gf * (Rq[ln] * kEX[q] + Rq[FL + ln] * kEY[q]);
         if constexpr (EXT) {
           if (kq != 0.0)  // the neighbour's Q reads psi here (Eq. 17)
-            fe += kq * (ring[slot][2][ln] * (kEX[q] * kEX[q]) + ring[slot][3][ln] * (kEY[q] * kEY[q]) +
-                        ring[slot][4][ln] * (kEX[q] * kEY[q]));
+            fe += kq * (Rq[2 * FL + ln] * (kEX[q] * kEX[q]) + Rq[3 * FL + ln] * (kEY[q] * kEY[q]) +
+                        Rq[4 * FL + ln] * (kEX[q] * kEY[q]));
         }
         acc += wa * fe * (A * pb + (1.0 - A) * pv[1 - kEY[q]][1 - kEX[q]]);
       }
       if (pb > 0.0) gpsi += acc * (-pb * 0.5 * d.two_over_Gpsi * 0.5);
-      const double rbar = acc * dpsi_drho(d, rb, pb);
-      const unsigned k = (unsigned)((wy(ys) - 1) * nx + x);
+      const double rbar = acc * db;
+      const unsigned k = rowk(ys) + (unsigned)x;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) lam0[i * n + k] = (T)(ldir[i][l] + rbar);
+      for (int i = 0; i < 9; ++i) {
+        double dir;
+        if constexpr (EXT) {
+          dir = ldir[ys & 1][i][l];
+        } else {
+          dir = hb;
+          if (kEX[i] != 0) dir += kEX[i] * hbx;
+          if (kEY[i] != 0) dir += kEY[i] * hby;
+          if (kept) dir = keep * (double)lsB[i] + dir;
+        }
+        lam0[i * n + k] = (T)(dir + rbar);
+      }
     };
     for (int yc = yc0; yc <= yc1; ++yc) {
-      // psi and rho of row yc+1 from its populations (loaded one iteration ago), or the ghost row's psi
-      if (fluid(yc + 1)) node_rho_psi(d, fB, re, pe);
+      // forward values of row yc+1 from its populations (loaded one iteration ago), or the ghost row's psi
+      double pe, de = 0.0, re = 0.0, jxe = 0.0, jye = 0.0;
+      if (fluid(yc + 1)) node(fN, re, jxe, jye, pe, de);
       else pe = pg;
-      // loads for later rows: populations (or the ghost row's psi) of row yc+2, lambda of row yc+1
+      // loads for later rows: populations (or the ghost row's psi) of row yc+2, lambda* of row yc+1
       const int r2 = yc + 2;
       double pgnext = 0.0;
       if (r2 <= yc1 + 1) {
         if (fluid(r2)) load_f(r2, fN);
-        else pgnext = act ? P.at(x, r2) : 0.0;
+        else pgnext = P.at(x, r2);
       }
       if (yc < yc1) load_lam(yc + 1, lsN);
-      // stage C at row yc: psi rows yc-1 (b), yc (c), yc+1 (e)
-      double bL, bR, cL, cR, eL, eR;
-      lr(pb, bL, bR);
-      lr(pc, cL, cR);
-      lr(pe, eL, eR);
-      double Fbx = 0.0, Fby = 0.0, qb[3] = {0.0, 0.0, 0.0};
-      if (act) {
-        double Fix, Fiy;
-        force_vals(d, bL, pb, bR, cL, cR, pc, eL, pe, eR, Fix, Fiy);
-        double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
-        if (mcw && yc == 1) Fy = Fy + gwb * pc;        // Eq. 14 next to the bottom wall
-        if (mcw && yc == ny - 2) Fy = Fy - gwt * pc;   // and next to the top wall
-        double gq = 0.0;
-        if (mrt) {
-          collide_mrt_adj(d, fA, lsA, Fx, Fy, lcur, Fbx, Fby, qb);
-          if (kq != 0.0) {  // Q is proportional to G_f: G_f_bar += Q_bar : Q / G_f
-            double qxx, qyy, qxy;
-            qtensor<double>(pc, cL, cR, pe, eL, eR, pb, bL, bR, A, kq, qxx, qyy, qxy);
-            gq = (qb[0] * qxx + qb[1] * qyy + qb[2] * qxy) / Gf;
-          }
-        } else {
-          collide_adj(d, fA, lsA, Fx, Fy, lcur, Fbx, Fby);
+      double eL, eR;
+      lane_lr(pe, eL, eR);
+      // 2. stage C at row yc: psi rows yc-1 (b), yc (c), yc+1 (e)
+      double Fix, Fiy;
+      force_vals(d, bL, pb, bR, cL, cR, pc, eL, pe, eR, Fix, Fiy);
+      double Fx = Fix + d.body_fx, Fy = Fiy + d.body_fy;
+      if (mcw && yc == 1) Fy = Fy + gwb * pc;        // Eq. 14 next to the bottom wall
+      if (mcw && yc == ny - 2) Fy = Fy - gwt * pc;   // and next to the top wall
+      double ls[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ls[i] = (double)lsA[i];
+      double Fbx, Fby, qb[3] = {0.0, 0.0, 0.0}, gq = 0.0, hc = 0.0, hcx = 0.0, hcy = 0.0;
+      if (mrt) {
+        double lam[9];
+        collide_mrt_adj(d, rc, jxc, jyc, ls, Fx, Fy, lam, Fbx, Fby, qb);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ldir[yc & 1][i % ND][l] = lam[i];
+        if (kq != 0.0) {  // Q is proportional to G_f: G_f_bar += Q_bar : Q / G_f (the division once per block)
+          double qxx, qyy, qxy;
+          qtensor<double>(pc, cL, cR, pe, eL, eR, pb, bL, bR, A, kq, qxx, qyy, qxy);
+          gq = qb[0] * qxx + qb[1] * qyy + qb[2] * qxy;
         }
-        if (own) {
-          if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) / Gf + gq;  // halo rows belong elsewhere
-          if (!py && (yc == 1 || yc == ny - 2)) {
-            FX.at(x, yc) = Fbx;
-            FY.at(x, yc) = Fby;
-            if (kq != 0.0) {
-              double* q = sc.qwall + (yc == 1 ? 0 : 3) * nx;
-              q[x] = qb[0];
-              q[nx + x] = qb[1];
-              q[2 * nx + x] = qb[2];
-            }
+      } else {
+        collide_adj(d, rc, jxc, jyc, ls, Fx, Fy, hc, hcx, hcy, Fbx, Fby);
+        if constexpr (EXT) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            double dir = hc;
+            if (kEX[i] != 0) dir += kEX[i] * hcx;
+            if (kEY[i] != 0) dir += kEY[i] * hcy;
+            ldir[yc & 1][i][l] = kept ? keep * ls[i] + dir : dir;
+          }
+        }
+      }
+      if (own) {
+        if (yc >= y0 && yc <= ylast) gf_part += (Fbx * Fix + Fby * Fiy) + gq;  // halo rows belong elsewhere
+        if (!py && (yc == 1 || yc == ny - 2)) {
+          FX.at(x, yc) = Fbx;
+          FY.at(x, yc) = Fby;
+          if (kq != 0.0) {
+            double* q = sc.qwall + (yc == 1 ? 0 : 3) * nx;
+            q[x] = qb[0];
+            q[nx + x] = qb[1];
+            q[2 * nx + x] = qb[2];
           }
         }
       }
       __syncthreads();  // the slot written next was read by stage S two rows back
-      ring[yc % 3][0][l] = Fbx;
-      ring[yc % 3][1][l] = Fby;
+      double* Rw = &ring[yc % 3][0][0];
+      Rw[l] = Fbx;
+      Rw[FL + l] = Fby;
       if constexpr (EXT) {
-        ring[yc % 3][2][l] = qb[0];
-        ring[yc % 3][3][l] = qb[1];
-        ring[yc % 3][4][l] = qb[2];
+        Rw[2 * FL + l] = qb[0];
+        Rw[3 * FL + l] = qb[1];
+        Rw[4 * FL + l] = qb[2];
       }
       __syncthreads();
-      // stage S at row yc-1: psi rows yc-2 (a), yc-1 (b), yc (c)
-      if (yc - 1 >= y0 && yc - 1 <= ylast) {
-        double aL, aR;
-        lr(pa, aL, aR);
-        if (own) stage_s(yc - 1, aL, aR, bL, bR, cL, cR);
-      }
+      // 3, 5. stage S at row yc-1: psi rows yc-2 (a), yc-1 (b), yc (c)
+      if (yc - 1 >= y0 && yc - 1 <= ylast && own) stage_s(yc - 1);
       // slide the window one row on
-      pa = pb; pb = pc; pc = pe;
-      rb = rc; rc = re;
+      pa = pb; aL = bL; aR = bR;
+      pb = pc; bL = cL; bR = cR;
+      pc = pe; cL = eL; cR = eR;
+      db = dc; dc = de;
+      rc = re; jxc = jxe; jyc = jye;
+      hb = hc; hbx = hcx; hby = hcy;
       pg = pgnext;
+      if (!EXT && kept) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        ldir[i][l] = lcur[i];  // same lane reads it back at the next stage S
-        fA[i] = fB[i];
-        fB[i] = (double)fN[i];
-        lsA[i] = (double)lsN[i];
+        for (int i = 0; i < 9; ++i) lsB[i] = lsA[i];
       }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lsA[i] = lsN[i];
     }
     // the top wall's boundary row: no stage C row above it (row ny-1 is the ghost row, F_bar absent there);
-    // after the slide the window holds psi rows ny-3 (a), ny-2 (b), ny-1 (c) and rho of row ny-2 in rb
-    if (!py && ylast == ny - 2) {
-      double aL, aR, bL, bR, cL, cR;
-      lr(pa, aL, aR);
-      lr(pb, bL, bR);
-      lr(pc, cL, cR);
-      if (own) stage_s(ylast, aL, aR, bL, bR, cL, cR);
-    }
+    // after the slide the window holds psi rows ny-3 (a), ny-2 (b), ny-1 (c)
+    if (!py && ylast == ny - 2 && own) stage_s(ylast);
     __syncthreads();  // the ring is reused by the next task
   }
-  const double tf = wave_sum(gf_part);  // one wavefront per block
+  const double tf = wave_sum(gf_part) / Gf;  // one wavefront per block; F (less F_body) is proportional to G_f
   const double tp = wave_sum(gpsi);
   if (threadIdx.x == 0) {
     sc.part[blockIdx.x] = tf;
@@ -622,33 +697,46 @@ __global__ __launch_bounds__(AB) void ka_finalize(AdjScratch sc, int nb_fluid, i
 int adjoint_partials_needed() { return 3 * kAdjBlocks; }
 
 namespace {
+// resident blocks (wavefronts) of the fused pass per compute unit, from its register and LDS use
+template <bool EXT, class T>
+int fused_blocks_per_cu() {
+  static const int b = [] {
+    int v = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, ka_fused<EXT, T>, FL, 0) == hipSuccess && v > 0 ? v : 8;
+  }();
+  return b;
+}
+
 template <class T>
 hipError_t launch_adjoint_t(const InstDesc* d_desc, const InstDesc& h, int inst, const AdjScratch& sc, const T* f_n,
                             const T* lam_np1, T* lam_n, double* theta_bar, double* G_bar, hipStream_t s) {
   const unsigned gghost = (unsigned)((2 * h.nx + AB - 1) / AB);
   if (gghost > (unsigned)kAdjBlocks) return hipErrorInvalidValue;
   // fused pass: column blocks of at most FL - 4 columns (balanced), and row strips sized so that the tasks fit
-  // in one round of resident wavefronts (eight per compute unit at this kernel's register use), at least 4 rows
+  // in one round of resident wavefronts (as many per compute unit as the kernel's register use allows), at least
+  // 4 rows
   static int cus = 0;
   if (cus == 0) {
     int dev = 0, v = 0;
     cus = (hipGetDevice(&dev) == hipSuccess &&
            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ? v : 256;
   }
+  const bool ext = h.mrt || h.wall_mc;
+  const int per_cu = ext ? fused_blocks_per_cu<true, T>() : fused_blocks_per_cu<false, T>();
   const int ncb = (h.nx + FL - 5) / (FL - 4);
   const int bw = (h.nx + ncb - 1) / ncb;
   const int nyf = h.ny - 2;
-  const int strips = std::max(1, std::min(nyf, 8 * cus / ncb));
+  const int strips = std::max(1, std::min(nyf, per_cu * cus / ncb));
   const int H = std::max(4, (nyf + strips - 1) / strips);
   const int ntasks = ncb * ((nyf + H - 1) / H);
-  const unsigned gfused = (unsigned)std::min(ntasks, kAdjBlocks);
+  const unsigned gfused = (unsigned)std::min((ntasks + 7) / 8 * 8, kAdjBlocks);  // a multiple of 8
   const bool walls = h.periodic_y == 0;  // periodic rows have no ghost rows and no wetting
   if (walls) {
     hipLaunchKernelGGL(ka_prep_rows<T>, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n,
                        sc);
     hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
   }
-  if (h.mrt || h.wall_mc)
+  if (ext)
     hipLaunchKernelGGL((ka_fused<true, T>), dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
                        H, ntasks);
   else
