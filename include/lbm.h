@@ -53,7 +53,15 @@ typedef enum {
 typedef enum {
   LBM_F64 = 0,         /* populations stored and computed in FP64 */
   LBM_F32 = 1,         /* populations stored and computed in FP32 */
-  LBM_F32_SHIFTED = 2  /* FP32 storage of f_i - w_i rho0 (rho0 = rho0_shift), computed in FP32 */
+  LBM_F32_SHIFTED = 2, /* FP32 storage of f_i - w_i rho0 (rho0 = rho0_shift), computed in FP32 */
+  LBM_F32_SHIFTED_MIXED = 3  /* FP32 storage of f_i - w_i rho0 (rho0 = rho0_shift, 0 = unshifted) as in
+                          LBM_F32_SHIFTED, and the same FP32 sums (density, momentum, the rest population from the
+                          mass balance), but psi from the FP64 EOS (Eq. 10, rounded to FP32) at every density and
+                          the force (Eq. 9), velocity, equilibrium and forcing terms (Eq. 1-6) in FP64; MRT (Eq. 15)
+                          is evaluated in FP64 throughout. Same memory traffic as the other FP32 modes; holds the
+                          density to the FP64 result over long runs where FP32 arithmetic drifts (the FP32 rounding of
+                          the force and the equilibrium accumulates over thousands of steps). rho_fp64_below is not
+                          used. */
 } lbm_precision;
 
 typedef enum {

@@ -6,8 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_E_INVALID, LBM_E_WORKSPACE, LBM_E_HIP, LBM_E_UNSTABLE, LBM_E_STATE, LBM_E_UNSUPPORTED = range(7)
-LBM_F64, LBM_F32, LBM_F32_SHIFTED = 0, 1, 2
-PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f32_shifted": LBM_F32_SHIFTED}
+LBM_F64, LBM_F32, LBM_F32_SHIFTED, LBM_F32_SHIFTED_MIXED = 0, 1, 2, 3
+PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f32_shifted": LBM_F32_SHIFTED, "f32_shifted_mixed": LBM_F32_SHIFTED_MIXED}
 
 
 class Params(C.Structure):

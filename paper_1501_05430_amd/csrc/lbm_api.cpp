@@ -278,7 +278,7 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
     if (q.nx < 2 || q.ny < 4) return bad("need nx >= 2 and ny >= 4");
     if ((int64_t)q.nx * q.ny > (int64_t)1 << 34) return bad("lattice too large");
     if (q.ny - 2 > 65535) return bad("ny too large");
-    if (q.precision < LBM_F64 || q.precision > LBM_F32_SHIFTED) return bad("unknown precision");
+    if (q.precision < LBM_F64 || q.precision > LBM_F32_SHIFTED_MIXED) return bad("unknown precision");
     if (q.precision != p[0].precision) return bad("all instances must share one precision");
     if (q.wet_iters < 0 || q.wet_iters > 1000) return bad("wet_iters out of range [0, 1000]");
     if (q.check_every < 0) return bad("check_every < 0");
@@ -310,7 +310,8 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
       if (!pw_from_params(q, &E)) return bad("piecewise EOS: Eq. 12-13 have no break points rho_v < rho_1 < rho_2 < rho_l");
     }
     if (!std::isfinite(q.rho0_shift) || q.rho0_shift < 0) return bad("rho0_shift must be >= 0");
-    if (q.precision != LBM_F32_SHIFTED && q.rho0_shift != 0) return bad("rho0_shift needs LBM_F32_SHIFTED");
+    if (q.precision != LBM_F32_SHIFTED && q.precision != LBM_F32_SHIFTED_MIXED && q.rho0_shift != 0)
+      return bad("rho0_shift needs LBM_F32_SHIFTED or LBM_F32_SHIFTED_MIXED");
     if (!std::isfinite(q.rho_fp64_below)) return bad("rho_fp64_below not finite");
     if (!std::isfinite(q.body_force[0]) || !std::isfinite(q.body_force[1])) return bad("body force not finite");
     for (int k = 0; k < 3; ++k)
@@ -465,9 +466,10 @@ struct lbm_ctx {
     return true;
   }
 
+  bool f32() const { return storage != STORE_F64; }
   // the two-step kernel covers the selection: FP32 storage, tau = 1 BGK and geometric walls everywhere
   bool step2_ok(int sel) const {
-    if (!step2 || storage != STORE_F32 || !tau1(sel)) return false;
+    if (!step2 || !f32() || !tau1(sel)) return false;
     for (int i = 0; i < n(); ++i)
       if ((sel < 0 || i == sel) && inst[i].p.boundary != LBM_WALLS_Y) return false;
     return true;
@@ -582,14 +584,14 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
   c->ws = (char*)d_workspace;
   c->ws_bytes = ws_bytes;
   c->stream = (hipStream_t)hip_stream;
-  c->storage = p[0].precision == LBM_F64 ? STORE_F64 : STORE_F32;
+  c->storage = p[0].precision == LBM_F64 ? STORE_F64 : (p[0].precision == LBM_F32_SHIFTED_MIXED ? STORE_F32M : STORE_F32);
   if (c->storage == STORE_F64) {
     c->waves = kDefaultWaves64;
     c->prefetch = kDefaultPrefetch64;
   }
   // two steps per launch by default for FP32 (where the selection allows it); variants 1..8 choose a one-step
   // shape, 9..12 the two-step kernel with 1, 2, 4 or 8 wavefronts per block
-  c->step2 = c->storage == STORE_F32;
+  c->step2 = c->f32();
   if (p[0].step_variant > 0 && p[0].step_variant <= 2 * kNumWaveChoices) {
     c->waves = kWaveChoices[(p[0].step_variant - 1) % kNumWaveChoices];
     c->prefetch = (p[0].step_variant - 1) / kNumWaveChoices == 1;
@@ -663,7 +665,7 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     d.force_pref = 1.0 - 0.5 / p[i].tau;
     d.body_fx = p[i].body_force[0];
     d.body_fy = p[i].body_force[1];
-    d.rho0 = p[i].precision == LBM_F32_SHIFTED ? p[i].rho0_shift : 0.0;
+    d.rho0 = (p[i].precision == LBM_F32_SHIFTED || p[i].precision == LBM_F32_SHIFTED_MIXED) ? p[i].rho0_shift : 0.0;
     d.rho_fp64_below = p[i].precision == LBM_F64 ? 0.0 : p[i].rho_fp64_below;
     d.rho_cap_hi = I.rho_cap * (1.0 - 1e-6);
     d.eos_kind = p[i].eos;
@@ -696,7 +698,8 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     // two-step kernel: one round of resident blocks over all instances, each task a tile of a strip; fewer, taller
     // strips than that leave compute units idle, more add a partial second round and more halo rows
     int per_cu = 0;
-    if (c->storage == STORE_F32 && step2_blocks_per_cu(c->waves2, &per_cu) == hipSuccess && per_cu > 0) {
+    if (c->f32() && step2_blocks_per_cu(c->waves2, c->storage == STORE_F32M, &per_cu) == hipSuccess &&
+        per_cu > 0) {
       const int wmax = 64 * c->waves2 - kStep2Halo;
       double tile_rows = 0;
       for (int i = 0; i < n_inst; ++i) tile_rows += (double)((p[i].nx + wmax - 1) / wmax) * (p[i].ny - 2);
@@ -853,7 +856,9 @@ int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check, int
   for (int64_t i = 0; i < count; ++nl) {
     const bool chk = chk_at(i);
     if (two && !chk && i + 1 < count && !chk_at(i + 1)) {
-      if (!dry) HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, (int)(nl & 1), c->stream));
+      if (!dry)
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage == STORE_F32M,
+                             (int)(nl & 1), c->stream));
       i += 2;
       continue;
     }
@@ -1196,7 +1201,8 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
     for (int k = 0; k <= launches; ++k) {
       if (k == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // launch 0 warms up
       if (two)
-        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, 0, c->stream));
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage == STORE_F32M, 0,
+                             c->stream));
       else
         HIP_TRY(launch_step(c->storage, false, c->tau1(inst), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a,
                             b - a, 0, c->d_wdiag() + a, c->stream, k & 1));
@@ -1254,7 +1260,7 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
     use2 = best2 < best;
     if (use2) best = best2;
   }
-  c->step2 = use2 || (c->storage == STORE_F32 && guard.step2 && !c->step2_ok(inst));
+  c->step2 = use2 || (c->f32() && guard.step2 && !c->step2_ok(inst));
   // 2. with several shape classes, refine each class's strip height in turn (the others held)
   if (shapes.size() > 1) {
     for (auto& kv : shapes) {

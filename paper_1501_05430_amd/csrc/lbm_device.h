@@ -36,6 +36,12 @@ __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ inline int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
+// Fused multiply-add a * b + c, rounded once. The step's arithmetic is written with these where it fuses and with
+// contraction off elsewhere, so that every kernel inlining it rounds identically, whatever the surrounding code
+// would let the compiler fuse (the one-step and two-step kernels must agree bit for bit).
+__device__ inline float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ------------------------------------------------------------------------------------------------ EOS / psi
 // p(rho) of the instance's EOS and psi = sqrt(2 (p - rho/3) / G) (Eq. 10 with c = 1); the argument is clamped at
 // 0 (counted) where it is negative. The EOS is Carnahan-Starling or the piecewise-linear one of Eq. 11; the choice
@@ -45,8 +51,8 @@ __device__ inline int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? 
 template <class T>
 __device__ inline T pw_pressure(const InstDesc& d, T rho) {
   if (rho <= (T)d.pw_r1) return rho * (T)d.pw_t[0];
-  if (rho <= (T)d.pw_r2) return (T)d.pw_p1 + (rho - (T)d.pw_r1) * (T)d.pw_t[1];
-  return (T)d.pw_p2 + (rho - (T)d.pw_r2) * (T)d.pw_t[2];
+  if (rho <= (T)d.pw_r2) return fmac(rho - (T)d.pw_r1, (T)d.pw_t[1], (T)d.pw_p1);
+  return fmac(rho - (T)d.pw_r2, (T)d.pw_t[2], (T)d.pw_p2);
 }
 
 // FP64 mode: IEEE division and square root.
@@ -83,34 +89,41 @@ __device__ inline double sqrt64(double x) {
   return fma(fma(-s, s, x), h, s);
 }
 
+// psi of an FP32 density from the FP64 EOS (refined hardware reciprocal and square root), rounded to FP32.
+__device__ inline float psi_f32_via64(const InstDesc& d, float rho, bool& clamped) {
+#pragma clang fp contract(off)
+  const double r = (double)rho;
+  double p;
+  if (d.eos_kind == 1) {
+    p = pw_pressure(d, r);
+  } else {
+    // Carnahan-Starling: 1 + e + e^2 - e^3 = 1 + e (1 + e (1 - e))
+    const double eta = d.eos_b4 * r;
+    const double om = 1.0 - eta;
+    const double poly = fmac(eta, fmac(eta, 1.0 - eta, 1.0), 1.0);
+    p = fmac(r * d.RT * poly, rcp64(om * om * om), -(d.eos_a * r) * r);
+  }
+  const double arg = d.two_over_Gpsi * fmac(r, -1.0 / 3.0, p);
+  clamped = arg < 0.0;
+  return (float)sqrt64(arg);
+}
+
 // FP32 modes: below rho_fp64_below the EOS is evaluated in FP64 (vapour side of a large density ratio),
 // elsewhere in FP32 with the hardware reciprocal and square root.
 __device__ inline float psi_f32(const InstDesc& d, float rho, bool& clamped) {
+#pragma clang fp contract(off)
   const bool pw = d.eos_kind == 1;
-  if (rho < (float)d.rho_fp64_below) {
-    const double r = (double)rho;
-    double p;
-    if (pw) {
-      p = pw_pressure(d, r);
-    } else {
-      const double eta = d.eos_b4 * r;
-      const double om = 1.0 - eta;
-      p = r * d.RT * (1.0 + eta + eta * eta - eta * eta * eta) * rcp64(om * om * om) - d.eos_a * r * r;
-    }
-    const double arg = d.two_over_Gpsi * (p - r * (1.0 / 3.0));
-    clamped = arg < 0.0;
-    return (float)sqrt64(arg);
-  }
+  if (rho < (float)d.rho_fp64_below) return psi_f32_via64(d, rho, clamped);
   float p;
   if (pw) {
     p = pw_pressure(d, rho);
   } else {
     const float eta = (float)d.eos_b4 * rho;
     const float om = 1.0f - eta;
-    p = rho * (float)d.RT * (1.0f + eta + eta * eta - eta * eta * eta) * __builtin_amdgcn_rcpf(om * om * om) -
-        (float)d.eos_a * rho * rho;
+    const float poly = fmac(eta, fmac(eta, 1.0f - eta, 1.0f), 1.0f);
+    p = fmac(rho * (float)d.RT * poly, __builtin_amdgcn_rcpf(om * om * om), -((float)d.eos_a * rho) * rho);
   }
-  float arg = (float)d.two_over_Gpsi * (p - rho * (1.0f / 3.0f));
+  float arg = (float)d.two_over_Gpsi * fmac(rho, -1.0f / 3.0f, p);
   clamped = arg < 0.0f;
   if (clamped) arg = 0.0f;
   return __builtin_amdgcn_sqrtf(arg);
@@ -136,50 +149,70 @@ __device__ inline C mom_y(const C (&f)[9]) {
   return (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
 }
 
-// BGK collision with Guo forcing (Eq. 1-6; at tau = 1 this is the relaxation matrix diag(0,1,...,1) of Sec. 3.1):
-//   v = (j + F/2)/rho, f*_i = f_i - (f_i - f_i^eq)/tau + (1 - 1/(2 tau)) w_i [3 (e_i - v) + 9 (e_i.v) e_i] . F,
-// f_i^eq = w_i rho (1 + 3 e_i.v + 4.5 (e_i.v)^2 - 1.5 v^2). Populations may be stored shifted by w_i rho0:
-// delta = rho - rho0 replaces rho in the zeroth-order term. Opposite directions share the even part
-// (w [delta - 1.5 rho v^2 + 4.5 rho (e.v)^2 + pref (9 (e.v)(e.F) - 3 v.F)]) and differ in the sign of the odd
-// part (w [3 rho e.v + 3 pref e.F]).
-// The rest population is taken from mass conservation, f*_0 = f_0 + sum_{i>0} (f_i - f*_i), which equals the
-// formula above in exact arithmetic. In rounded arithmetic the node's mass then changes by one rounding of f*_0
-// only: evaluating w_0 [...] directly adds a bias every step (the rounded weights do not sum to one, and the
-// -1.5 rho v^2 term falls below the rounding unit in slow regions), which in FP32 drifts the total mass by about
-// 1e-8 per step.
-template <class C, bool TAU1>
-__device__ inline void collide(const C (&f)[9], C rho, C delta, C Fx, C Fy, C inv_tau, C pref, C irho, C (&fs)[9]) {
-  const C w1 = (C)(1.0 / 9.0), w2 = (C)(1.0 / 36.0);
-  const C jx = mom_x(f), jy = mom_y(f);
-  const C vx = (jx + (C)0.5 * Fx) * irho;
-  const C vy = (jy + (C)0.5 * Fy) * irho;
-  const C vF = vx * Fx + vy * Fy;
-  const C eq0 = delta - (C)1.5 * rho * (vx * vx + vy * vy);  // zeroth + second-order isotropic part of f_eq
-  const C fo0 = -(C)3 * pref * vF;                          // isotropic part of the forcing
-  const C r45 = (C)4.5 * rho, r3 = (C)3 * rho, p9 = (C)9 * pref, p3 = (C)3 * pref;
-  auto put = [&](int i, int o, C w, C eu, C eF) {
-    const C se = eq0 + r45 * eu * eu;          // even part of f_eq / w
-    const C sf = fo0 + p9 * eu * eF;           // even part of the forcing / w
-    const C ae = r3 * eu, af = p3 * eF;        // odd parts
+// Interaction force of Eq. 9 (plus the body force) from psi of the centre (pc), its row neighbours (L, R) and the
+// rows below (m) and above (n), in the arithmetic type T. Evaluated without fused multiply-adds and with
+// psi_R^2 - psi_L^2 = (psi_R - psi_L)(psi_R + psi_L), so the rounded force is exactly odd under x -> -x and
+// y -> -y, as the exact one is (a fused a*a - b*b is not the negative of b*b - a*a).
+template <class T>
+__device__ inline void hybrid_force(const InstDesc& d, T pc, T pcL, T pcR, T pm, T pmL, T pmR, T pn, T pnL, T pnR,
+                                    T& Fx, T& Fy) {
+#pragma clang fp contract(off)
+  const T k1 = (T)(1.0 / 3.0), k2 = (T)(1.0 / 12.0), A = (T)d.A, Gf = (T)d.G_f;
+  const T spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
+  const T spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
+  const T sux = k1 * ((pcR - pcL) * (pcR + pcL)) + k2 * ((pnR - pnL) * (pnR + pnL) + (pmR - pmL) * (pmR + pmL));
+  const T suy = k1 * ((pn - pm) * (pn + pm)) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
+  Fx = -Gf * ((T)0.5 * A * sux + ((T)1 - A) * pc * spx) + (T)d.body_fx;
+  Fy = -Gf * ((T)0.5 * A * suy + ((T)1 - A) * pc * spy) + (T)d.body_fy;
+}
+
+// psi of the FP32 storage modes: LBM_F32 / LBM_F32_SHIFTED evaluate the EOS in FP32 (in FP64 below
+// rho_fp64_below); LBM_F32_SHIFTED_MIXED (MIX) always in FP64, rounded to FP32.
+template <bool MIX, class C>
+__device__ inline C node_psi(const InstDesc& d, C rho, bool& cl) {
+  if constexpr (MIX) return psi_f32_via64(d, rho, cl);
+  else return psi_eval(d, rho, cl);
+}
+
+// The rounding is spelled out: no contraction, and the fused multiply-adds written where they are wanted, so that
+// every kernel inlining this (one step or two steps per launch, any arithmetic) rounds identically, whatever the
+// surrounding code would let the compiler fuse. Each fused form is even or odd under the mirrors as its exact value
+// is. C is the type of the populations and of the sums over them (momentum, and the rest population's mass
+// balance); A the type of everything between: velocity, equilibrium and forcing (A = C except in
+// LBM_F32_SHIFTED_MIXED, where A is double for FP32 populations).
+template <class C, class A, bool TAU1>
+__device__ inline void collide(const C (&f)[9], A rho, A delta, A Fx, A Fy, A inv_tau, A pref, A irho, C (&fs)[9]) {
+#pragma clang fp contract(off)
+  const A w1 = (A)(1.0 / 9.0), w2 = (A)(1.0 / 36.0);
+  const A jx = (A)mom_x(f), jy = (A)mom_y(f);
+  const A vx = fmac((A)0.5, Fx, jx) * irho;
+  const A vy = fmac((A)0.5, Fy, jy) * irho;
+  const A vF = fmac(vx, Fx, vy * Fy);
+  const A eq0 = fmac((A)-1.5 * rho, fmac(vx, vx, vy * vy), delta);  // zeroth + second-order isotropic part of f_eq
+  const A fo0 = -(A)3 * pref * vF;                                  // isotropic part of the forcing
+  const A r45 = (A)4.5 * rho, r3 = (A)3 * rho, p9 = (A)9 * pref, p3 = (A)3 * pref;
+  auto put = [&](int i, int o, A w, A eu, A eF) {
+    const A se = fmac(r45 * eu, eu, eq0);      // even part of f_eq / w
+    const A sf = fmac(p9 * eu, eF, fo0);       // even part of the forcing / w
     if (TAU1) {
-      fs[i] = w * ((se + sf) + (ae + af));
-      fs[o] = w * ((se + sf) - (ae + af));
+      const A odd = fmac(r3, eu, p3 * eF);     // odd parts of f_eq and the forcing / w
+      fs[i] = (C)(w * ((se + sf) + odd));
+      fs[o] = (C)(w * ((se + sf) - odd));
     } else {
-      fs[i] = f[i] + (w * (se + ae) - f[i]) * inv_tau + w * (sf + af);
-      fs[o] = f[o] + (w * (se - ae) - f[o]) * inv_tau + w * (sf - af);
+      const A ae = r3 * eu, af = p3 * eF;      // odd parts
+      const A fi = (A)f[i], fo = (A)f[o];
+      fs[i] = (C)(fmac(w * (se + ae) - fi, inv_tau, fi) + w * (sf + af));
+      fs[o] = (C)(fmac(w * (se - ae) - fo, inv_tau, fo) + w * (sf - af));
     }
   };
   put(1, 3, w1, vx, Fx);
   put(2, 4, w1, vy, Fy);
   put(5, 7, w2, vx + vy, Fx + Fy);
   put(6, 8, w2, vy - vx, Fy - Fx);
-  {
-    // the differences must see the rounded f*_i that are stored: no fusing of their products into these sums
-#pragma clang fp contract(off)
-    const C d13 = (f[1] - fs[1]) + (f[3] - fs[3]), d24 = (f[2] - fs[2]) + (f[4] - fs[4]);
-    const C d57 = (f[5] - fs[5]) + (f[7] - fs[7]), d68 = (f[6] - fs[6]) + (f[8] - fs[8]);
-    fs[0] = f[0] + ((d13 + d24) + (d57 + d68));
-  }
+  // the differences see the rounded f*_i that are stored
+  const C d13 = (f[1] - fs[1]) + (f[3] - fs[3]), d24 = (f[2] - fs[2]) + (f[4] - fs[4]);
+  const C d57 = (f[5] - fs[5]) + (f[7] - fs[7]), d68 = (f[6] - fs[6]) + (f[8] - fs[8]);
+  fs[0] = f[0] + ((d13 + d24) + (d57 + d68));
 }
 
 // MRT collision of Eq. 15 with Lambda = diag(0, s_e, s_eps, 1, s_q, 1, s_q, 1/tau, 1/tau) (Eq. 2), the forcing
@@ -263,6 +296,7 @@ __device__ inline void qtensor(C p, C pL, C pR, C pn, C pnL, C pnR, C pm, C pmL,
 // Eq. 20. T is the tangential difference of the boundary row, D = rho_2 - rho_1. Clamped to [0, rho_cap_hi].
 __device__ inline double ghost_density(double rL, double rR, double r1, double r2, double c, double cot, int iters,
                                        double cap_hi, bool& clamped) {
+#pragma clang fp contract(off)
   const double T = rR - rL;
   double r0;
   if (iters == 0) {

@@ -54,7 +54,8 @@ struct InstDiag {
   long long checks, nonfinite, psi_clamps, ghost_clamps, pad;
 };
 
-enum { STORE_F64 = 0, STORE_F32 = 1 };
+// state storage: FP64, FP32 (FP32 arithmetic), FP32 with the mixed arithmetic of LBM_F32_SHIFTED_MIXED
+enum { STORE_F64 = 0, STORE_F32 = 1, STORE_F32M = 2 };
 
 // Launch helpers implemented in lbm_kernels.hip. All return the hipError_t of the launch.
 // waves: wavefronts per block (1, 2, 4 or 8; the tasks must have been built for it); tau1: specialised collision
@@ -69,10 +70,11 @@ hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefe
 // Two steps per launch (lbm_step2.hip): FP32 storage, tau = 1 BGK, geometric walls (every instance of the launch).
 // Tasks are tiles: output columns [x0, x0 + width) with width <= 64 waves - 6 (the kernel adds three halo columns
 // per side), output rows [y0, y0 + nrows). Reads buffer cur ^ flip, writes the other one (as one one-step launch).
-hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip,
+// mix: the mixed arithmetic of LBM_F32_SHIFTED_MIXED (STORE_F32M).
+hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, bool mix, int flip,
                         hipStream_t s);
 // Resident blocks of the two-step kernel per compute unit (hipOccupancyMaxActiveBlocksPerMultiprocessor).
-hipError_t step2_blocks_per_cu(int waves, int* blocks);
+hipError_t step2_blocks_per_cu(int waves, bool mix, int* blocks);
 hipError_t launch_finalize_diag(const WaveTask* d_tasks, const int32_t* d_inst_first, int ninst_sel, int inst0,
                                 const WaveDiag* d_wdiag, InstDiag* d_idiag, const InstDesc* d_desc,
                                 hipStream_t s);

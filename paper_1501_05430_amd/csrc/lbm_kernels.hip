@@ -18,6 +18,8 @@
 //  * Each population is read once and written once per step (plus halo reads served by L2/MALL):
 //    72 B (FP32) / 144 B (FP64) of HBM traffic per lattice update at the roofline.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 
 #include "lbm_device.h"
@@ -27,12 +29,13 @@ namespace lbm {
 namespace {
 
 // ------------------------------------------------------------------------------------------------ step kernel
-template <class S, bool CHECK, bool TAU1, int W, bool PF, bool DOWN>
+template <class S, bool CHECK, bool TAU1, int W, bool PF, bool DOWN, bool MIX>
 __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ descs,
                                                    const WaveTask* __restrict__ tasks, int ntasks, int flip,
                                                    WaveDiag* __restrict__ wdiag) {
   typedef typename ComputeOf<S>::type C;
   typedef typename Gbl<S>::T GS;
+  static_assert(!MIX || std::is_same<S, float>::value, "the mixed arithmetic is a form of FP32 storage");
   const int task = (int)blockIdx.x;
   if (task >= ntasks) return;  // uniform over the block
   const int lane = threadIdx.x & (WAVE - 1);
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
       for (int i = 0; i < 9; ++i) f[i] = (C)0;
     }
     rho = rho0 + sum9(f);
-    psi = psi_eval(d, rho, cl);
+    psi = node_psi<MIX>(d, rho, cl);
     hrho = (C)0;
     hpsi = (C)0;
     if (edge) {
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
       gather<S, C>(gin, plane, pitch, nx, ny, hcol, wrapy(y), g, py);
       hrho = rho0 + sum9(g);
       bool dm;
-      hpsi = psi_eval(d, hrho, dm);
+      hpsi = node_psi<MIX>(d, hrho, dm);
     }
   };
 
@@ -142,9 +145,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
     gh_psi = (C)psi_eval(d, rh0, dm);
   };
 
-  const C A = (C)d.A, Gf = (C)d.G_f, inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
-  const C bfx = (C)d.body_fx, bfy = (C)d.body_fy;
-  const C k1 = (C)(1.0 / 3.0), k2 = (C)(1.0 / 12.0);
+  const C A = (C)d.A, inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
   // MRT collision with the surface-tension source (never in the tau = 1 BGK specialisation)
   const bool mrt = !TAU1 && d.mrt != 0, kap = mrt && d.kq != 0.0;
   const C s_e = (C)d.s_e, s_eps = (C)d.s_eps, s_q = (C)d.s_q, kq = (C)d.kq;
@@ -214,33 +215,46 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
       // psi of the rows below (m) and above (n) row y
       const C pm = DOWN ? pa : pb, pmL = DOWN ? paL : pbL, pmR = DOWN ? paR : pbR;
       const C pn = DOWN ? pb : pa, pnL = DOWN ? pbL : paL, pnR = DOWN ? pbR : paR;
-      // Interaction force, Eq. 9: F = -G_f [ (A/2) sum w psi_n^2 e + (1 - A) psi sum w psi_n e ].
-      C Fx, Fy;
-      {
-        // Evaluated without fused multiply-adds and with psi_R^2 - psi_L^2 = (psi_R - psi_L)(psi_R + psi_L), so
-        // the rounded force is exactly odd under x -> -x and y -> -y, as the exact one is; a fused a*a - b*b is
-        // not the negative of b*b - a*a.
-#pragma clang fp contract(off)
-        const C spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
-        const C spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
-        const C sux = k1 * ((pcR - pcL) * (pcR + pcL)) +
-                      k2 * ((pnR - pnL) * (pnR + pnL) + (pmR - pmL) * (pmR + pmL));
-        const C suy = k1 * ((pn - pm) * (pn + pm)) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
-        Fx = -Gf * ((C)0.5 * A * sux + ((C)1 - A) * pc * spx) + bfx;
-        Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
+      // Interaction force, Eq. 9: F = -G_f [ (A/2) sum w psi_n^2 e + (1 - A) psi sum w psi_n e ] (plus the body
+      // force), then the collision; for MIX the force, velocity, equilibrium and forcing in FP64
+      C fs[9];
+      if constexpr (MIX) {
+        double Fx, Fy;
+        hybrid_force<double>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
+        // Eq. 14 next to a flat solid row: sum_a w_a S(x + e_a) e_a = (0, -1/2) below, (0, 1/2) above
+        if (mcw) {
+          if (y == 1) Fy = Fy + d.gw_half[0] * (double)pc;
+          if (y == ny - 2) Fy = Fy - d.gw_half[1] * (double)pc;
+        }
+        if (mrt) {
+          double fd[9], fsd[9], qxx = 0.0, qyy = 0.0, qxy = 0.0;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fd[i] = (double)fc[i];
+          const double r = (double)rc;
+          if (kap) qtensor<double>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, d.A, d.kq, qxx, qyy, qxy);
+          collide_mrt<double>(fd, r, r - d.rho0, Fx, Fy, rcp64(r), d.s_e, d.s_eps, d.s_q, d.inv_tau, qxx, qyy, qxy,
+                              fsd);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fs[i] = (C)fsd[i];
+        } else {
+          const double r = (double)rc;
+          collide<C, double, TAU1>(fc, r, r - d.rho0, Fx, Fy, d.inv_tau, d.force_pref, rcp64(r), fs);
+        }
+      } else {
+        C Fx, Fy;
+        hybrid_force<C>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
         // Eq. 14 next to a flat solid row: sum_a w_a S(x + e_a) e_a = (0, -1/2) below, (0, 1/2) above
         if (mcw) {
           if (y == 1) Fy = Fy + gwb * pc;
           if (y == ny - 2) Fy = Fy - gwt * pc;
         }
-      }
-      C fs[9];
-      if (mrt) {
-        C qxx = (C)0, qyy = (C)0, qxy = (C)0;
-        if (kap) qtensor<C>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, A, kq, qxx, qyy, qxy);
-        collide_mrt<C>(fc, rc, rc - rho0, Fx, Fy, (C)1 / rc, s_e, s_eps, s_q, inv_tau, qxx, qyy, qxy, fs);
-      } else {
-        collide<C, TAU1>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
+        if (mrt) {
+          C qxx = (C)0, qyy = (C)0, qxy = (C)0;
+          if (kap) qtensor<C>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, A, kq, qxx, qyy, qxy);
+          collide_mrt<C>(fc, rc, rc - rho0, Fx, Fy, (C)1 / rc, s_e, s_eps, s_q, inv_tau, qxx, qyy, qxy, fs);
+        } else {
+          collide<C, C, TAU1>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
+        }
       }
       const unsigned off = (unsigned)((y - 1) * pitch + col);
 #pragma unroll
@@ -277,11 +291,11 @@ __global__ __launch_bounds__(WAVE * W) void k_step(const InstDesc* __restrict__ 
         for (int i = 0; i < 9; ++i) fn[i] = (C)0;
       }
       ra = rho0 + sum9(fn);
-      pa = psi_eval(d, ra, cl_a);
+      pa = node_psi<MIX>(d, ra, cl_a);
       C hpa = (C)0;
       if (edge) {
         bool dm;
-        hpa = psi_eval(d, rho0 + sum9(g), dm);
+        hpa = node_psi<MIX>(d, rho0 + sum9(g), dm);
       }
       xchg(pa, hpa, paL, paR);
     } else {
@@ -622,34 +636,34 @@ __global__ void k_set_cur(InstDesc* __restrict__ d, int inst, int cur) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
-template <class S, bool CHECK, bool TAU1, bool PF, bool DOWN>
+template <class S, bool CHECK, bool TAU1, bool PF, bool DOWN, bool MIX>
 void launch_step_d(int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc, const WaveTask* d_tasks,
                    int ntasks, int flip, WaveDiag* d_wdiag) {
   switch (waves) {
-    case 1: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 1, PF, DOWN>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-    case 2: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 2, PF, DOWN>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-    case 4: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 4, PF, DOWN>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
-    default: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 8, PF, DOWN>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    case 1: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 1, PF, DOWN, MIX>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    case 2: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 2, PF, DOWN, MIX>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    case 4: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 4, PF, DOWN, MIX>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
+    default: hipLaunchKernelGGL((k_step<S, CHECK, TAU1, 8, PF, DOWN, MIX>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, d_wdiag); break;
   }
 }
 
 // down: walk the strips downwards (see k_step)
-template <class S, bool CHECK, bool TAU1, bool PF>
+template <class S, bool CHECK, bool TAU1, bool PF, bool MIX>
 void launch_step_w(int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc, const WaveTask* d_tasks,
                    int ntasks, int flip, WaveDiag* d_wdiag, bool down) {
-  if (down) launch_step_d<S, CHECK, TAU1, PF, true>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
-  else launch_step_d<S, CHECK, TAU1, PF, false>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+  if (down) launch_step_d<S, CHECK, TAU1, PF, true, MIX>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
+  else launch_step_d<S, CHECK, TAU1, PF, false, MIX>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag);
 }
 
-template <class S, bool PF>
+template <class S, bool PF, bool MIX>
 void launch_step_s(bool check, bool tau1, int waves, unsigned grid, hipStream_t s, const InstDesc* d_desc,
                    const WaveTask* d_tasks, int ntasks, int flip, WaveDiag* d_wdiag, bool down) {
   if (check) {
-    if (tau1) launch_step_w<S, true, true, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
-    else launch_step_w<S, true, false, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
+    if (tau1) launch_step_w<S, true, true, PF, MIX>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
+    else launch_step_w<S, true, false, PF, MIX>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
   } else {
-    if (tau1) launch_step_w<S, false, true, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
-    else launch_step_w<S, false, false, PF>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
+    if (tau1) launch_step_w<S, false, true, PF, MIX>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
+    else launch_step_w<S, false, false, PF, MIX>(waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, down);
   }
 }
 
@@ -662,11 +676,14 @@ hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefe
   const unsigned grid = (unsigned)ntasks;
   const bool dn = down < 0 ? (flip & 1) != 0 : down != 0;  // consecutive steps alternate by default
   if (storage == STORE_F64) {
-    if (prefetch) launch_step_s<double, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
-    else launch_step_s<double, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    if (prefetch) launch_step_s<double, true, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    else launch_step_s<double, false, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+  } else if (storage == STORE_F32M) {
+    if (prefetch) launch_step_s<float, true, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    else launch_step_s<float, false, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
   } else {
-    if (prefetch) launch_step_s<float, true>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
-    else launch_step_s<float, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    if (prefetch) launch_step_s<float, true, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
+    else launch_step_s<float, false, false>(check, tau1, waves, grid, s, d_desc, d_tasks, ntasks, flip, d_wdiag, dn);
   }
   return hipGetLastError();
 }

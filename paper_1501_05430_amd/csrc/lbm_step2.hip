@@ -30,7 +30,7 @@ namespace {
 
 constexpr int kXcds = 8;
 
-template <int W>
+template <int W, bool MIX>
 __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__ descs,
                                                     const WaveTask* __restrict__ tasks, int ntasks, int flip) {
   typedef float C;
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
       for (int i = 0; i < 9; ++i) f[i] = (C)0;
     }
     rho = rho0 + sum9(f);
-    psi = psi_eval(d, rho, cl);
+    psi = node_psi<MIX>(d, rho, cl);
     hrho = (C)0;
     hpsi = (C)0;
     if (edge) {
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
       gather<S, C>(gin, plane, pitch, nx, ny, hcol, y, g);
       hrho = rho0 + sum9(g);
       bool dm;
-      hpsi = psi_eval(d, hrho, dm);
+      hpsi = node_psi<MIX>(d, hrho, dm);
     }
   };
   // ghost row beside wall `wall` from the boundary row yb (r1, halo hr1) and the second row (r2, hr2), Sec. 4
@@ -143,21 +143,22 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
     gh_psi = (C)psi_eval(d, rh0, dm);
   };
 
-  const C A = (C)d.A, Gf = (C)d.G_f, inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
-  const C bfx = (C)d.body_fx, bfy = (C)d.body_fy;
-  const C k1 = (C)(1.0 / 3.0), k2 = (C)(1.0 / 12.0);
+  const C inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
 
-  // Eq. 9 from psi of the centre (pc), its row neighbours and the rows below (m) and above (n); written as in the
-  // one-step kernel (no fused multiply-adds; exactly odd under both mirrors).
-  auto force = [&](C pc, C pcL, C pcR, C pm, C pmL, C pmR, C pn, C pnL, C pnR, C& Fx, C& Fy) {
-#pragma clang fp contract(off)
-    const C spx = k1 * (pcR - pcL) + k2 * ((pnR - pnL) + (pmR - pmL));
-    const C spy = k1 * (pn - pm) + k2 * ((pnR + pnL) - (pmR + pmL));
-    const C sux = k1 * ((pcR - pcL) * (pcR + pcL)) +
-                  k2 * ((pnR - pnL) * (pnR + pnL) + (pmR - pmL) * (pmR + pmL));
-    const C suy = k1 * ((pn - pm) * (pn + pm)) + k2 * ((pnR * pnR + pnL * pnL) - (pmR * pmR + pmL * pmL));
-    Fx = -Gf * ((C)0.5 * A * sux + ((C)1 - A) * pc * spx) + bfx;
-    Fy = -Gf * ((C)0.5 * A * suy + ((C)1 - A) * pc * spy) + bfy;
+  // Eq. 9 and the collision of one node (tau = 1 BGK), as in the one-step kernel: FP32, or for MIX the force,
+  // velocity, equilibrium and forcing in FP64
+  auto force_collide = [&](const C (&f)[9], C rho, C pc, C pcL, C pcR, C pm, C pmL, C pmR, C pn, C pnL, C pnR,
+                           C (&fs)[9]) {
+    if constexpr (MIX) {
+      double Fx, Fy;
+      hybrid_force<double>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
+      const double r = (double)rho;
+      collide<C, double, true>(f, r, r - d.rho0, Fx, Fy, d.inv_tau, d.force_pref, rcp64(r), fs);
+    } else {
+      C Fx, Fy;
+      hybrid_force<C>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
+      collide<C, C, true>(f, rho, rho - rho0, Fx, Fy, inv_tau, pref, (C)1 / rho, fs);
+    }
   };
 
   // step A's rows: those step B reads, g^{t+1} of rows y0 - 2 .. ylast + 2 within the fluid rows
@@ -217,9 +218,8 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
     bool slid = false;
     if (y <= ya1) {
       if (act) {
-        C Fx, Fy, fs[9];
-        force(pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, Fx, Fy);
-        collide<C, true>(fc, rc, rc - rho0, Fx, Fy, inv_tau, pref, (C)1 / rc, fs);
+        C fs[9];
+        force_collide(fc, rc, pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, fs);
         const int s = y % 3;
 #pragma unroll
         for (int i = 0; i < 9; ++i) gA[s][i][lx] = fs[i];
@@ -238,9 +238,9 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
           if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
           bool dm;
           ra = rho0 + sum9(fn);
-          pa = psi_eval(d, ra, dm);
+          pa = node_psi<MIX>(d, ra, dm);
           C hpa = (C)0;
-          if (edge) hpa = psi_eval(d, rho0 + sum9(g), dm);
+          if (edge) hpa = node_psi<MIX>(d, rho0 + sum9(g), dm);
           xput(pa, hpa);
           slid = true;
         } else {
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
       fg[8] = top ? gA[sc][6][lx] : gA[sp][8][lx - 1];
       rj = rho0 + sum9(fg);
       bool dm;
-      psB[sc][lx] = psi_eval(d, rj, dm);
+      psB[sc][lx] = node_psi<MIX>(d, rj, dm);
       if (bot) rhB[0][lx] = rj;
       if (top) rhB[1][lx] = rj;
     }
@@ -295,11 +295,10 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
     // ---- step B: collide row m = y - 2 (gathered in the previous iteration) and store it
     const int m = y - 2;
     if (m >= y0 && m <= ylast && actBc) {
-      C Fx, Fy, fs[9];
+      C fs[9];
       const int s0 = (m + 2) % 3, s1 = m % 3, s2 = (m + 1) % 3;  // rows m - 1, m, m + 1
-      force(psB[s1][lx], psB[s1][lx - 1], psB[s1][lx + 1], psB[s0][lx], psB[s0][lx - 1], psB[s0][lx + 1],
-            psB[s2][lx], psB[s2][lx - 1], psB[s2][lx + 1], Fx, Fy);
-      collide<C, true>(fBp, rBp, rBp - rho0, Fx, Fy, inv_tau, pref, (C)1 / rBp, fs);
+      force_collide(fBp, rBp, psB[s1][lx], psB[s1][lx - 1], psB[s1][lx + 1], psB[s0][lx], psB[s0][lx - 1],
+                    psB[s0][lx + 1], psB[s2][lx], psB[s2][lx - 1], psB[s2][lx + 1], fs);
       const unsigned off = (unsigned)((m - 1) * pitch + col);
 #pragma unroll
       for (int i = 0; i < 9; ++i) ((GS*)(gout + i * plane))[off] = fs[i];
@@ -311,33 +310,45 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
   }
 }
 
-template <int W>
+template <int W, bool MIX>
 int occupancy_of(int* blocks) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<W>, WAVE * W, 0);
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<W, MIX>, WAVE * W, 0);
+}
+
+template <bool MIX>
+hipError_t blocks_per_cu(int waves, int* blocks) {
+  switch (waves) {
+    case 1: return (hipError_t)occupancy_of<1, MIX>(blocks);
+    case 2: return (hipError_t)occupancy_of<2, MIX>(blocks);
+    case 4: return (hipError_t)occupancy_of<4, MIX>(blocks);
+    default: return (hipError_t)occupancy_of<8, MIX>(blocks);
+  }
+}
+
+template <bool MIX>
+void launch2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip, unsigned grid,
+             hipStream_t s) {
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_step2<1, MIX>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 2: hipLaunchKernelGGL((k_step2<2, MIX>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 4: hipLaunchKernelGGL((k_step2<4, MIX>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    default: hipLaunchKernelGGL((k_step2<8, MIX>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+  }
 }
 
 }  // namespace
 
-hipError_t step2_blocks_per_cu(int waves, int* blocks) {
+hipError_t step2_blocks_per_cu(int waves, bool mix, int* blocks) {
   *blocks = 0;
-  switch (waves) {
-    case 1: return (hipError_t)occupancy_of<1>(blocks);
-    case 2: return (hipError_t)occupancy_of<2>(blocks);
-    case 4: return (hipError_t)occupancy_of<4>(blocks);
-    default: return (hipError_t)occupancy_of<8>(blocks);
-  }
+  return mix ? blocks_per_cu<true>(waves, blocks) : blocks_per_cu<false>(waves, blocks);
 }
 
-hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip,
+hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, bool mix, int flip,
                         hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(((ntasks + kXcds - 1) / kXcds) * kXcds);
-  switch (waves) {
-    case 1: hipLaunchKernelGGL((k_step2<1>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 2: hipLaunchKernelGGL((k_step2<2>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 4: hipLaunchKernelGGL((k_step2<4>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    default: hipLaunchKernelGGL((k_step2<8>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-  }
+  if (mix) launch2<true>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  else launch2<false>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
   return hipGetLastError();
 }
 

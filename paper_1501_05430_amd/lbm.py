@@ -16,7 +16,8 @@ def make_params(nx, ny, T_over_Tc, *, precision="f64", wet_iters=4, check_every=
                 enable_adjoint=False, step_variant=0, tau=1.0, G=-1.0, A=-0.6, eos_a=1.0, eos_b=4.0, eos_R=1.0, rho0_shift=0.0,
                 rho_fp64_below=0.0, body_force=(0.0, 0.0), boundary="walls", piecewise=None, mrt=None, kappa=0.0,
                 G_w=(0.0, 0.0)):
-    """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32' or 'f32_shifted'; boundary: 'walls'
+    """lbm_params of one lattice (see include/lbm.h). precision: 'f64', 'f32', 'f32_shifted' or 'f32_shifted_mixed'
+    (FP32 storage, FP64 force and equilibrium); boundary: 'walls'
     (ghost rows 0 and ny-1 with the geometric wetting), 'periodic' (fluid rows 1..ny-2 wrap around) or
     'martys_chen' (solid walls with the fluid-solid force of Eq. 14, strengths G_w = (bottom, top)).
     piecewise = (theta_v, theta_m, theta_l, rho_v, rho_l) selects the piecewise-linear EOS of Eq. 11 (break points
@@ -61,15 +62,15 @@ def eos_coexistence(T_over_Tc, device="cuda:0", **eos):
 
 def fp32_options(T_over_Tc, precision, shift="rho_v", device="cuda:0", **eos):
     """make_params keywords of the FP32 modes: the EOS in FP64 below the geometric mean of the coexistence
-    densities, and for 'f32_shifted' the reference density rho0 of the stored f_i - w_i rho0 ('rho_v', 'rho_l' or
-    a number). The vapour density is the default shift: it keeps the vapour's populations small (their relative
+    densities, and for 'f32_shifted' and 'f32_shifted_mixed' the reference density rho0 of the stored f_i - w_i rho0
+    ('rho_v', 'rho_l' or a number). The vapour density is the default shift: it keeps the vapour's populations small (their relative
     rounding is then that of the deviation from rho_v), while the liquid's populations are no larger than
     unshifted ones."""
     if precision == "f64":
         return {}
     rv, rl = eos_coexistence(T_over_Tc, device=device, **eos)
     out = {"rho_fp64_below": math.sqrt(rv * rl)}
-    if precision == "f32_shifted":
+    if precision in ("f32_shifted", "f32_shifted_mixed"):
         out["rho0_shift"] = {"rho_v": rv, "rho_l": rl}.get(shift, shift)
     return out
 

@@ -79,6 +79,14 @@ def test_workspace_bytes_and_validation():
     q.eos = 2
     with pytest.raises(P.LbmError):
         P.workspace_bytes(q)
+    q = P.make_params(20, 10, 0.8)
+    q.precision = 4
+    with pytest.raises(P.LbmError):
+        P.workspace_bytes(q)
+    # the mixed-arithmetic mode stores FP32 populations (shifted or not): the FP32 workspace
+    for shift in (0.0, 0.3):
+        pm = P.make_params(200, 100, 0.85, precision="f32_shifted_mixed", rho0_shift=shift)
+        assert P.workspace_bytes(pm) == P.workspace_bytes(p32)
 
 
 TABLE1 = [(0.25, -0.02, 0.3, 1.0, 10.0), (0.1633, -0.02, 0.33333, 1.0, 100.0), (0.2, -0.01, 0.33333, 1.0, 1000.0)]

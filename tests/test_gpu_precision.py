@@ -1,11 +1,12 @@
 """Precision forms at the workloads' full sizes, through the C-ABI.
 
 * 1024 x 512 droplet (T = 0.7 T_c, R = 120, theta in {30, 60, 90, 120, 150} deg): 200-step FP64 and 100-step FP32
-  slices against the FP64 CPU reference over the whole lattice, then the full 20 000-step runs of FP32 (unshifted,
-  shifted by rho_v, shifted by rho_l) against FP64 on the GPU: contact angle, mass, and the density difference,
-  whose growth is printed (run with -s to see it).
+  slices against the FP64 CPU reference over the whole lattice, then the full 20 000-step runs of the FP32 forms
+  (FP32 arithmetic: unshifted, shifted by rho_v, shifted by rho_l; the mixed form shifted by rho_v) against FP64 on
+  the GPU: contact angle, mass, and the density difference, whose growth is printed (run with -s to see it).
 * 4096 x 2048 lattice (T = 0.5 T_c, 65 droplets) in the benchmark's launch configuration: 100 steps of FP64 and of
-  FP32 shifted by rho_v with the FP64 EOS near the vapour, against the CPU reference over the whole lattice.
+  the FP32 forms shifted by rho_v against the CPU reference over the whole lattice, and the full 10 000 steps of the
+  FP32 forms against FP64 on the GPU.
 * Mirror symmetry: a droplet symmetric about x = nx/2 (and a free one also about the mid-plane between two equal
   walls) stays exactly symmetric, bit for bit, in every precision.
 """
@@ -25,12 +26,14 @@ BOX = (0, 1024, 1, 400)          # region of the bottom-wall droplet for the con
 TOL64 = 1e-12                    # FP64: max|drho| / max rho
 TOL32 = 1e-5                     # FP32: max|drho| / rho_l over a slice
 THETA_TOL = 0.5                  # FP32: contact angle, degrees
-# FP32: |m - m0| / m0 over 20 000 steps. Shifting by the liquid density stores the vapour's populations as
+# FP32 forms: |m - m0| / m0 over 20 000 steps. Shifting by the liquid density stores the vapour's populations as
 # w_i (rho - rho_l), about 60 times larger than unshifted ones at this density ratio, with rounding to match.
-MASS32 = {None: 1e-6, "rho_v": 1e-6, "rho_l": 2e-5}
+FP32_MODES = [("f32", None), ("f32_shifted", "rho_v"), ("f32_shifted", "rho_l"), ("f32_shifted_mixed", "rho_v")]
+MASS32 = dict(zip(FP32_MODES, (1e-6, 1e-6, 2e-5, 1e-6)))
 MASS64 = 1e-13
-LONG32 = {None: 3e-4, "rho_v": 3e-4, "rho_l": 3e-3}   # FP32 within 20 000 steps: max|drho| / rho_l (see below)
-FP32_MODES = [("f32", None), ("f32_shifted", "rho_v"), ("f32_shifted", "rho_l")]
+# FP32 forms within 20 000 steps: max|drho| / rho_l. FP32 arithmetic accumulates its rounding of the force and the
+# equilibrium (see test_c2_fp32_full_run_vs_fp64); the mixed form holds the stated 1e-5.
+LONG32 = dict(zip(FP32_MODES, (3e-4, 3e-4, 3e-3, TOL32)))
 
 
 def coexistence(T):
@@ -69,7 +72,7 @@ def test_c2_slices_vs_reference(deg):
     case = W.c2_angle(deg)
     ref = oracle_sim(case)
     s64 = gpu_sim(case, precision="f64")
-    s32 = [gpu_sim(case, precision=p) for p in ("f32", "f32_shifted")]
+    s32 = [gpu_sim(case, precision=p) for p in ("f32", "f32_shifted", "f32_shifted_mixed")]
     rv, rl = ref.coexistence()
     ref.run(100)
     r100, _ = ref.density()
@@ -82,7 +85,8 @@ def test_c2_slices_vs_reference(deg):
         s.close()
     s64.step(200)
     e64 = np.abs(s64.rho()[1:-1] - r200[1:-1]).max() / np.abs(r200[1:-1]).max()
-    print(f"\n  c2 theta={deg}: FP64 200 steps {e64:.1e}, FP32 / FP32 shifted 100 steps {e32[0]:.1e} / {e32[1]:.1e}")
+    print(f"\n  c2 theta={deg}: FP64 200 steps {e64:.1e}, FP32 / shifted / mixed 100 steps {e32[0]:.1e} / {e32[1]:.1e}"
+          f" / {e32[2]:.1e}")
     s64.close()
     assert e64 <= TOL64, e64
     assert max(e32) <= TOL32, e32
@@ -95,7 +99,7 @@ def test_c2_fp64_full_run_conserves_mass(c2_fp64, deg):
     assert drift <= MASS64, drift
 
 
-@pytest.mark.parametrize("mode", FP32_MODES, ids=["f32", "shift_rho_v", "shift_rho_l"])
+@pytest.mark.parametrize("mode", FP32_MODES, ids=["f32", "shift_rho_v", "shift_rho_l", "mixed_rho_v"])
 @pytest.mark.parametrize("deg", ANGLES)
 def test_c2_fp32_full_run_vs_fp64(c2_fp64, deg, mode):
     ref = c2_fp64(deg)
@@ -110,22 +114,25 @@ def test_c2_fp32_full_run_vs_fp64(c2_fp64, deg, mode):
           f", mass drift {drift:.1e}, max|drho|/rho_l at {CHECKS} = {['%.1e' % e for e in errs]}"
           f", vapour max|drho|/rho at the end {evap:.1e}")
     assert dth <= THETA_TOL, dth
-    assert drift <= MASS32[mode[1]], drift
-    # Over a 100-step slice the FP32 densities stay within 1e-5 of the reference (test above). Within the full run
-    # the round-off of FP32 storage, injected every step (about 6e-8 relative), builds up during the spreading
-    # transient to about 1e-4 of rho_l and decays as the droplet settles; a single 1e-7 perturbation of an FP64 run
-    # stays at 1e-7, so this is accumulation, not amplification.
-    assert max(errs) <= LONG32[mode[1]], errs
+    assert drift <= MASS32[mode], drift
+    # Over a 100-step slice every FP32 form stays within 1e-5 of the reference (test above). Over the full run FP32
+    # arithmetic drifts to several 1e-5 of rho_l: its rounding of the force and of the equilibrium, about 6e-8
+    # relative, is injected every step and acts coherently, while an FP64 run perturbed once by rounding its state
+    # to FP32 stays within 1e-6 and relaxes (accumulation, not amplification). The mixed form evaluates those in
+    # FP64 and holds 1e-5 over the whole run.
+    assert max(errs) <= LONG32[mode], errs
 
 
-def test_c4_sampled_fp32_instances_vs_reference():
-    """The 256-instance batch in FP32 shifted by rho_v (FP64 EOS below sqrt(rho_v rho_l)), all instances in each
-    launch (two steps per launch), 100 steps: 8 instances drawn with the seed, each against the FP64 reference over
-    its own lattice, max |drho| / rho_l <= 1e-5 (the vapour-relative error is printed)."""
+@pytest.mark.parametrize("precision", ["f32_shifted", "f32_shifted_mixed"])
+def test_c4_sampled_fp32_instances_vs_reference(precision):
+    """The 256-instance batch in FP32 shifted by rho_v (FP32 arithmetic with the FP64 EOS below sqrt(rho_v rho_l),
+    or the mixed form), all instances in each launch (two steps per launch), 100 steps: 8 instances drawn with the
+    seed, each against the FP64 reference over its own lattice, max |drho| / rho_l <= 1e-5 (the vapour-relative
+    error is printed)."""
     import paper_1501_05430_amd as P
     cases = W.c4_batch()
-    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision="f32_shifted",
-                            **P.fp32_options(c.T_over_Tc, "f32_shifted")) for c in cases]
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision=precision,
+                            **P.fp32_options(c.T_over_Tc, precision)) for c in cases]
     batch = P.LBM(params)
     for i, c in enumerate(cases):
         batch.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
@@ -160,7 +167,7 @@ def c3_reference():
     return case, rho[1:-1].copy(), rl
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32_shifted"])
+@pytest.mark.parametrize("precision", ["f64", "f32_shifted", "f32_shifted_mixed"])
 def test_c3_full_size_vs_reference(c3_reference, precision):
     """The benchmark's configuration (device check every 100 steps, default block shape) over 100 steps.
 
@@ -185,6 +192,28 @@ def test_c3_full_size_vs_reference(c3_reference, precision):
     assert err <= tol, err
 
 
+def test_c3_fp32_forms_over_the_full_run():
+    """The 4096 x 2048 workload's 10 000 steps in the benchmark's launch configuration: the FP32 forms shifted by
+    rho_v against FP64 on the GPU. At this density ratio (about 1000) the FP32 storage's own rounding accumulates:
+    measured max |drho| / rho_l 1.4e-3 with FP32 arithmetic and 1.4e-4 in the mixed form (an FP64 run whose state
+    is rounded to FP32 once stays within 8.5e-6 over the same 10 000 steps; FP64 arithmetic throughout, with the
+    same storage, reaches 1.6e-4). Held to 3e-3 and 3e-4."""
+    case = W.c3_large()
+    out = {}
+    for precision in ("f64", "f32_shifted", "f32_shifted_mixed"):
+        sim = gpu_sim(case, precision=precision, check_every=100)
+        rl = sim.coexistence()[1]
+        sim.step(10000)
+        out[precision] = sim.rho()[1:-1]
+        d = sim.diag()
+        sim.close()
+        assert d["nonfinite"] == 0, precision
+    err = {p: float(np.abs(out[p] - out["f64"]).max() / rl) for p in ("f32_shifted", "f32_shifted_mixed")}
+    print(f"\n  c3 10 000 steps: max|drho|/rho_l FP32 shifted {err['f32_shifted']:.2e}, mixed {err['f32_shifted_mixed']:.2e}")
+    assert err["f32_shifted_mixed"] <= 3e-4, err
+    assert err["f32_shifted"] <= 3e-3, err
+
+
 def mirrored(rho, axis):
     """rho [fluid rows, nx] under x -> nx - x (periodic, axis 1) or the mid-plane mirror between the walls."""
     if axis == 1:
@@ -192,7 +221,7 @@ def mirrored(rho, axis):
     return rho[::-1]
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "f32_shifted"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_shifted", "f32_shifted_mixed"])
 def test_wall_droplet_stays_mirror_symmetric_bitwise(precision):
     case = W.c2_angle(150)
     sim = gpu_sim(case, precision=precision)
@@ -203,7 +232,7 @@ def test_wall_droplet_stays_mirror_symmetric_bitwise(precision):
     sim.close()
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "f32_shifted"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32_shifted", "f32_shifted_mixed"])
 def test_free_droplet_stays_mirror_symmetric_bitwise(precision):
     nx, ny = 128, 130                       # fluid rows 1..128: mirror y <-> 129 - y about y = 64.5
     th = np.full(nx, math.radians(60.0))
@@ -254,18 +283,21 @@ def test_c2_thirty_degrees_offset_does_not_depend_on_resolution():
     assert all(abs(v - 30.0) <= 3.1 for v in th.values()), th
 
 
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])
 @pytest.mark.parametrize("ratio", [100, 1000])
-def test_fp32_in_the_papers_setting_tracks_fp64(ratio):
+def test_fp32_in_the_papers_setting_tracks_fp64(ratio, mixed):
     """The paper's own model (Table 1 EOS, kappa = 0.5 with Lambda = diag(0,1,...,1): the MRT form) on the 1024 x 512
     geometry with a 60 deg cap of radius 120, 20 000 steps: FP32 storage shifted by rho_v (FP64 EOS below
     sqrt(rho_v rho_l)) against FP64 on the GPU. Measured: the angles agree to 0.001 deg (59.83 / 59.59 deg at ratios
     100 / 1000), FP32 mass drift 2e-8 / 7e-9, density difference 2.3e-5 / 1.9e-5 of rho_l. Checked: angle within
-    0.5 deg, FP32 mass drift within 1e-6, density difference within 2e-4 of rho_l."""
+    0.5 deg, FP32 mass drift within 1e-6, density difference within 2e-4 of rho_l with FP32 arithmetic and within
+    1e-5 in the mixed form (whose MRT collision is FP64 throughout)."""
     import paper_1501_05430_amd as P
     pw = {100: (0.1633, -0.02, 0.33333, 1.0, 100.0), 1000: (0.2, -0.01, 0.33333, 1.0, 1000.0)}[ratio]
     case = W.c2_angle(60)
     out = {}
-    for precision in ("f64", "f32_shifted"):
+    p32 = "f32_shifted_mixed" if mixed else "f32_shifted"
+    for precision in ("f64", p32):
         sim = P.LBM(P.make_params(case.nx, case.ny, 1.0, precision=precision, piecewise=pw, kappa=0.5,
                                   check_every=1000, **P.fp32_options(1.0, precision, piecewise=pw)))
         sim.apply_wetting(case.theta_bottom, case.theta_top)
@@ -276,11 +308,11 @@ def test_fp32_in_the_papers_setting_tracks_fp64(ratio):
         out[precision] = (sim.rho()[1:-1], abs(sim.mass() - m0) / m0, th, sim.diag())
         sim.close()
     r64, d64, th64, g64 = out["f64"]
-    r32, d32, th32, g32 = out["f32_shifted"]
+    r32, d32, th32, g32 = out[p32]
     err = np.abs(r32 - r64).max() / pw[4]
-    print(f"\n  ratio {ratio}: theta FP64 {th64:.3f} / FP32 {th32:.3f}, mass drift FP64 {d64:.1e} / FP32 {d32:.1e}, "
-          f"max|drho|/rho_l {err:.1e}")
+    print(f"\n  ratio {ratio} {p32}: theta FP64 {th64:.3f} / FP32 {th32:.3f}, mass drift FP64 {d64:.1e} / FP32 "
+          f"{d32:.1e}, max|drho|/rho_l {err:.1e}")
     assert g64["nonfinite"] == 0 and g32["nonfinite"] == 0
     assert abs(th32 - th64) <= THETA_TOL
     assert d64 <= MASS64 and d32 <= 1e-6
-    assert err <= 2e-4
+    assert err <= (TOL32 if mixed else 2e-4), err
