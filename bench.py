@@ -31,6 +31,93 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
               for n in ("lbm_step2.hip", "lbm_device.h", "lbm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")
 TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step2_f32_batched_c4.json")
+TRAFFIC_FILE_MIXED = os.path.join(ROOT, "profiles", "traffic_step2_mixed_c3.json")
+
+
+# HBM-traffic summaries of the step kernel (profiles/traffic_<name>.json), made from two rocprofv3 counter runs of
+# this script (FETCH_SIZE, then WRITE_SIZE) by `bench.py --traffic-summary <name>`
+TRAFFIC_SPECS = {
+    "step2_f32_c3": dict(
+        match="k_step2<4, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        desc="k_step2<W=4> (two time steps per launch; FP32 storage shifted by rho_v, FP32 arithmetic with the FP64 "
+             "EOS in the vapour, tau = 1 BGK, geometric walls), 4096x2048 lattice, T = 0.5 T_c, theta = 45 deg, "
+             "65 droplets; default shape"),
+    "step2_mixed_c3": dict(
+        match="k_step2<4, true>", workload="c3",
+        args="--precision f32_shifted_mixed --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        desc="k_step2<W=4> in the mixed form (FP32 storage shifted by rho_v and FP32 sums; psi, force, equilibrium "
+             "and forcing in FP64), same lattice and shape"),
+    "step2_f32_batched_c4": dict(
+        match="k_step2<", exclude=", true>", workload="c4", args="--batched-only --steps 40",
+        desc="k_step2 (two time steps per launch, the autotuner's block shape) over the 256-instance batch (sizes "
+             "64x32 .. 512x256, T/T_c in [0.6, 0.9], theta in [20, 160] deg, seed 1501), FP32 shifted by rho_v"),
+}
+COPY_KERNEL = "k_copy<HIP_vector_type<float, 4u> >"
+
+
+def traffic_summary(name):
+    """profiles/traffic_<name>.json from gpurun_out/prof_<name>_fetch and _write (rocprofv3 --pmc FETCH_SIZE /
+    WRITE_SIZE of `bench.py <args>`): the kernel's HBM bytes per launch, each counter scaled by what it reads for
+    the float4 copy of known size that the same run performs (bandwidth_ceilings); runs without that copy take the
+    scale of the step2_f32_c3 summary."""
+    import csv
+    from paper_1501_05430_amd import workloads as W
+    spec = TRAFFIC_SPECS[name]
+    runs = {}
+    for counter, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        path = os.path.join(ROOT, "gpurun_out", f"prof_{name}_{tag}", "p_counter_collection.csv")
+        with open(path) as f:
+            rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+        kern = [float(r["Counter_Value"]) for r in rows
+                if spec["match"] in r["Kernel_Name"] and not (spec.get("exclude") and spec["exclude"] in r["Kernel_Name"])]
+        copy = [float(r["Counter_Value"]) for r in rows if COPY_KERNEL in r["Kernel_Name"]]
+        runs[counter] = (sum(kern) / len(kern), len(kern), sum(copy) / len(copy) if copy else None)
+    if spec["workload"] == "c3":
+        case = W.c3_large()
+        nodes = case.fluid_nodes
+        pitch = (case.nx + 63) // 64 * 64
+        state_bytes = 4 * 9 * (case.ny - 2) * pitch
+    else:
+        nodes = sum(c.fluid_nodes for c in W.c4_batch())
+        state_bytes = None
+    if runs["FETCH_SIZE"][2] is not None and state_bytes:
+        calib = {"kernel": f"{COPY_KERNEL} of the bench's bandwidth_ceilings (bw_probe.hip), {state_bytes:,} bytes "
+                           "copied per dispatch",
+                 "fetch_kib": round(runs["FETCH_SIZE"][2], 3), "write_kib": round(runs["WRITE_SIZE"][2], 3),
+                 "fetch_scale": round(state_bytes / (1024 * runs["FETCH_SIZE"][2]), 4),
+                 "write_scale": round(state_bytes / (1024 * runs["WRITE_SIZE"][2]), 4)}
+    else:
+        with open(os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")) as f:
+            calib = dict(json.load(f)["calibration"])
+        calib["kernel"] += " (taken from the step2_f32_c3 run)"
+    rd = runs["FETCH_SIZE"][0] * 1024 * calib["fetch_scale"]
+    wr = runs["WRITE_SIZE"][0] * 1024 * calib["write_scale"]
+    alg = 2 * 72 * nodes
+    out = {
+        "kernel": spec["desc"],
+        "kernel_source_sha256": kernel_sha(),
+        "kernel_sources": [os.path.relpath(p_, ROOT) for p_ in KERNEL_SRC],
+        "commands": [f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof_{name}_{t} -o p -- python3 bench.py "
+                     f"{spec['args']}" for c, t in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))]
+                    + [f"python3 bench.py --traffic-summary {name}"],
+        "calibration": calib,
+        "kernel_counters_kib_per_launch": {"FETCH_SIZE": round(runs["FETCH_SIZE"][0], 1),
+                                           "WRITE_SIZE": round(runs["WRITE_SIZE"][0], 1),
+                                           "launches_averaged": runs["FETCH_SIZE"][1]},
+        "time_steps_per_launch": 2,
+        "hbm_read_bytes_per_launch": int(rd),
+        "hbm_write_bytes_per_launch": int(wr),
+        "hbm_bytes_per_launch": int(rd + wr),
+        "algorithmic_bytes_per_launch": alg,
+        "traffic_over_algorithmic": round((rd + wr) / alg, 4),
+    }
+    if state_bytes:
+        out["state_bytes"] = state_bytes
+    dst = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    with open(dst, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"wrote": os.path.relpath(dst, ROOT), "traffic_over_algorithmic": out["traffic_over_algorithmic"]}))
 
 
 def kernel_sha():
@@ -159,11 +246,13 @@ def cpu_baseline(case, target_s=15.0, max_steps=400):
 
 
 def error_vs_oracle(case, ref):
-    """The headline configuration (FP32 shifted) and FP64, each stepped on the GPU as far as the CPU reference went
-    from the same initial state: max |rho - rho_ref| / rho_l (FP32) and / max rho_ref (FP64) over the fluid rows."""
+    """The headline configuration (FP32 shifted), the mixed FP32 form and FP64, each stepped on the GPU as far as
+    the CPU reference went from the same initial state: max |rho - rho_ref| / rho_l (FP32 forms) and
+    / max rho_ref (FP64) over the fluid rows."""
     steps, rho_ref, rho_l = ref
     out = {"steps": steps}
     for precision, scale, key in (("f32_shifted", rho_l, "f32_shifted_max_drho_over_rho_l"),
+                                  ("f32_shifted_mixed", rho_l, "f32_shifted_mixed_max_drho_over_rho_l"),
                                   ("f64", np.abs(rho_ref).max(), "f64_max_drho_rel")):
         sim = make_sim(case, precision, check_every=100)
         sim.step(steps)
@@ -311,6 +400,21 @@ def piecewise_rate(case, steps=2000, kappa=0.0):
             "mass_drift": abs(m1 - m0) / m0}
 
 
+def mixed_rate(case, steps=1000):
+    """The FP32 storage form with the force and equilibrium in FP64 (LBM_F32_SHIFTED_MIXED) on the same lattice,
+    in the same launch configuration: the same 72 B per fluid node and step."""
+    sim = make_sim(case, "f32_shifted_mixed", check_every=100)
+    sim.step(50)
+    ms, stable = timed_steps(sim, steps)
+    d = sim.diag()
+    sim.close()
+    nodes = case.fluid_nodes
+    ach = 72 * nodes * steps / ms / 1e6
+    return {"mlups": round(nodes * steps / ms / 1e3, 1), "gbs_alg": round(ach, 1),
+            "frac_of_hbm_peak": round(ach / PEAK_HBM_GBS, 4), "steps": steps,
+            "stable": stable and d["nonfinite"] == 0}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,7 +428,14 @@ def main():
                     help="run only the 256-instance batched leg and print its JSON (for profiling that launch)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint legs on the headline lattice and print their JSON (for profiling)")
+    ap.add_argument("--precision", default="f32_shifted", choices=["f32_shifted", "f32_shifted_mixed"],
+                    help="the timed form: FP32 arithmetic (default) or the mixed form (FP64 force and equilibrium)")
+    ap.add_argument("--traffic-summary", metavar="NAME", choices=sorted(TRAFFIC_SPECS),
+                    help="write profiles/traffic_NAME.json from the two counter runs under gpurun_out/ and exit")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the method on a single MI355X "
               f"(asked for --gpus {args.gpus}).", file=sys.stderr)
@@ -347,7 +458,7 @@ def main():
 
     case = W.c3_large()
     ceilings = bandwidth_ceilings(case.nx, case.ny)
-    sim = make_sim(case, "f32_shifted", check_every=100)
+    sim = make_sim(case, args.precision, check_every=100)
     if args.autotune:
         sim.autotune(trial_steps=10)
     sim.step(args.warmup)
@@ -361,7 +472,8 @@ def main():
     bytes_alg = 72 * nodes  # 9 FP32 populations read + 9 written per fluid node and step
     achieved = bytes_alg / (ms_step * 1e-3) / 1e9
 
-    traffic, per_launch = profile_traffic(TRAFFIC_FILE)
+    mixed = args.precision == "f32_shifted_mixed"
+    traffic, per_launch = profile_traffic(TRAFFIC_FILE_MIXED if mixed else TRAFFIC_FILE)
 
     out = {
         "metric": "MLUPS & % HBM roofline; FP32/batched/adjoint vs plain FP64 at stated error",
@@ -374,11 +486,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64" if mixed else "f32",
         "data": "synthetic",
         "config": {
             "workload": case.name, "nx": case.nx, "ny": case.ny, "fluid_nodes": nodes, "T_over_Tc": 0.5,
-            "theta_deg": 45, "droplets": len(case.xc), "seed": W.SEED, "precision": "f32_shifted (rho0 = rho_v; FP64 EOS in vapour)",
+            "theta_deg": 45, "droplets": len(case.xc), "seed": W.SEED, "precision": ("f32_shifted_mixed (rho0 = rho_v; FP32 storage and sums, FP64 psi, force and "
+                                                          "equilibrium)" if mixed else
+                                                          "f32_shifted (rho0 = rho_v; FP64 EOS in vapour)"),
             "check_every": 100, "stable": stable, "mass_at_last_check": diag["mass"],
             "measured_theta_deg": round(math.degrees(theta[0]), 3),
         },
@@ -387,7 +501,7 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
             # current), traffic_gbs those bytes over this run's time per launch
-            "kernel": "k_step2 (two time steps per launch)", "steps_per_launch": 2,
+            "kernel": f"k_step2<4, {'true' if mixed else 'false'}> (two time steps per launch)", "steps_per_launch": 2,
             "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic
@@ -404,6 +518,7 @@ def main():
         out["extras"] = {
             "fp64_same_lattice": {"mlups": round(nodes * 1000 / ms64 / 1e3, 1),
                                   "gbs_alg": round(144 * nodes * 1000 / ms64 / 1e6, 1), "stable": st64},
+            "f32_shifted_mixed_same_lattice": mixed_rate(case),
             "batched_256": batched_vs_plain(),
             "adjoint_fp64_same_lattice": adjoint_rate(case),
             "adjoint_fp32_storage_same_lattice": adjoint_rate(case, dtype="f32"),
