@@ -88,7 +88,9 @@ typedef struct lbm_ctx lbm_ctx; /* opaque; holds host memory only */
 
 /* Parameters of one lattice instance. Defaults in brackets are the paper's / the workloads' values. */
 typedef struct {
-  int32_t nx, ny;         /* columns (periodic) and rows including both ghost rows; nx >= 2, ny >= 4 */
+  int32_t nx, ny;         /* columns (periodic) and rows including both ghost rows; nx >= 2, ny >= 4,
+                             ny - 2 <= 65535, and pitch x (ny - 2) < 2^31 with pitch = nx rounded up to 64 (about
+                             2.1e9 fluid nodes: 155 GB of FP32 populations) */
   int32_t precision;      /* lbm_precision; every instance of a context must use the same one */
   int32_t wet_iters;      /* 0: Eq. 19; k >= 1: k-th iterate of Eq. 21 (first line = iterate 1) [4] */
   int32_t check_every;    /* steps between device checks of mass, non-finite density and clamps; 0 = none */

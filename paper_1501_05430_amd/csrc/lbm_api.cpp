@@ -288,7 +288,9 @@ bool valid_params(const lbm_params* p, int32_t n, std::string* why) {
       return bad("unknown boundary");
     if (!std::isfinite(q.G_w[0]) || !std::isfinite(q.G_w[1])) return bad("G_w not finite");
     if (q.eos != LBM_EOS_CARNAHAN_STARLING && q.eos != LBM_EOS_PIECEWISE_LINEAR) return bad("unknown eos");
-    if ((int64_t)((q.nx + 63) / 64 * 64) * (q.ny - 2) * 9 >= ((int64_t)1 << 31)) return bad("lattice too large for 32-bit offsets");
+    // offsets inside a population plane are 32-bit in the kernels (planes are 64-bit apart)
+    if ((int64_t)((q.nx + 63) / 64 * 64) * (q.ny - 2) >= ((int64_t)1 << 31))
+      return bad("lattice too large: pitch x (ny - 2) must stay below 2^31");
     if (!(q.tau > 0.5) || !std::isfinite(q.tau)) return bad("tau must be > 0.5");
     if (!(q.G < 0) || !std::isfinite(q.G)) return bad("G must be negative");
     if (!std::isfinite(q.A)) return bad("A not finite");

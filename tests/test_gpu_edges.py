@@ -1,5 +1,5 @@
 """Edge cases through the C-ABI: an empty lattice (no droplet), the smallest lattices, the largest lattice the
-32-bit offsets allow (checked through properties that hold at any size), and calls out of order."""
+in-plane 32-bit offsets allow (checked through properties that hold at any size), and calls out of order."""
 import math
 
 import numpy as np
@@ -50,30 +50,34 @@ def test_smallest_lattices_match_reference(ora, nx, ny, steps, drop):
     assert err <= 1e-12, err
 
 
-@pytest.mark.parametrize("precision", ["f32_shifted", "f64"])
-def test_largest_lattice(precision):
-    """16384 columns x 14563 fluid rows (9 * pitch * rows just below 2^31): 20 steps with a droplet centred at
-    x = nx/2 run without a fault or a non-finite value, conserve mass and stay mirror-symmetric bit for bit."""
+@pytest.mark.parametrize("precision,nx,nyf", [("f32_shifted", 32768, 65535), ("f64", 16384, 32768)])
+def test_largest_lattice(precision, nx, nyf):
+    """Lattices past the 2^31 elements of a whole state: in FP32 the largest one the in-plane 32-bit offsets allow
+    (32768 x 65535 fluid rows, pitch x rows just below 2^31: 2.1e9 nodes, 155 GB of populations), in FP64 16384 x
+    32768 (5.4e8 nodes, 77 GB). 20 steps with a droplet centred at x = nx/2 run without a fault or a non-finite
+    value, conserve mass and stay mirror-symmetric bit for bit; one more row (or a wider plane) is refused."""
     import torch
     import paper_1501_05430_amd as P
-    nx = 16384
-    nyf = (2 ** 31 - 1) // (9 * nx)
     kw = P.fp32_options(0.7, precision)
-    with pytest.raises(P.LbmError):   # one more row exceeds the offsets
-        P.workspace_bytes(P.make_params(nx, nyf + 3, 0.7, precision=precision, **kw))
+    if precision == "f32_shifted":   # one more row exceeds the offsets
+        with pytest.raises(P.LbmError):
+            P.workspace_bytes(P.make_params(nx + 64, nyf + 2, 0.7, precision=precision, **kw))
     sim = P.LBM(P.make_params(nx, nyf + 2, 0.7, precision=precision, check_every=10, **kw))
+    R = nyf / 5
     sim.apply_wetting(math.radians(60.0), math.radians(90.0))
-    sim.init_droplet([nx / 2, nx / 2], [0.5 - 3000 * math.cos(math.radians(60.0)), 9000.0], [3000.0, 1500.0])
+    sim.init_droplet([nx / 2, nx / 2], [0.5 - R * math.cos(math.radians(60.0)), 3 * R], [R, R / 2])
     m0 = sim.mass()
     sim.step(20)
     d = sim.diag()
     m1 = sim.mass()
     r = sim.rho(device=True)[1:-1]
     mirror = torch.remainder(-torch.arange(nx, device=r.device), nx)
-    symmetric = bool(torch.equal(r, r.index_select(1, mirror)))
+    symmetric = all(bool(torch.equal(r[k:k + 4096], r[k:k + 4096].index_select(1, mirror)))
+                    for k in range(0, r.shape[0], 4096))
     finite = bool(torch.isfinite(r).all())
     del r
     sim.close()
+    torch.cuda.empty_cache()
     assert d["nonfinite"] == 0 and finite
     assert abs(m1 - m0) / m0 <= (1e-12 if precision == "f64" else 1e-6)
     assert symmetric
@@ -101,7 +105,7 @@ def test_calls_out_of_order_are_errors():
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_adjoint_at_the_largest_lattice(storage):
-    """16384 columns x 14563 fluid rows (9 * nx * rows just below 2^31; up to about 130 GB of device memory), both
+    """16384 columns x 14563 fluid rows (2.4e8 nodes, FP64 state; up to about 130 GB of device memory), both
     storage forms of the reverse step, two exact properties at every node. The step conserves mass, so the
     cotangent lambda = 1 (the derivative of the total mass) comes back as lambda = 1 with no angle or G gradient;
     and the reverse step is linear, so doubling lambda doubles every output bit for bit."""
