@@ -238,6 +238,26 @@ int lbm_set_state(lbm_ctx* c, int32_t inst, const void* d_src);
  * Synchronizes. */
 int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen);
 
+/* The step shape of a context: what lbm_autotune chose (or the defaults), to keep and re-apply later without the
+ * trials (the Python binding keeps a JSON cache of these records, keyed by the device and the instances). */
+typedef struct {
+  int32_t two_step;  /* 1: two time steps per launch wherever the selection allows it (FP32 storage, tau = 1 BGK,
+                        geometric walls); 0: one step per launch */
+  int32_t waves;     /* one-step kernel: wavefronts per block, 1, 2, 4 or 8 */
+  int32_t prefetch;  /* one-step kernel: 1 = the next row's loads in flight, 0 = not */
+  int32_t waves2;    /* two-step kernel: wavefronts per block, 1, 2, 4 or 8 */
+} lbm_tuning;
+
+/* Reads the context's shape into *t and, when the arrays are non-NULL, every instance's rows per strip of the
+ * one-step and the two-step kernel (n_inst entries each, the count lbm_create was given). Host only. */
+int lbm_get_tuning(const lbm_ctx* c, lbm_tuning* t, int32_t* strip_rows, int32_t* strip_rows2);
+
+/* Applies a shape read by lbm_get_tuning (from this or another context with the same instances): wavefronts in
+ * {1, 2, 4, 8}, prefetch and two_step 0 or 1, rows per strip >= 1 (NULL arrays keep the current rows; two_step
+ * is ignored for FP64 storage). LBM_E_INVALID on any other value, with nothing changed. Results do not depend on
+ * the shape (bitwise); the context's captured graphs are dropped. Stream-ordered: uploads the task tables. */
+int lbm_set_tuning(lbm_ctx* c, const lbm_tuning* t, const int32_t* strip_rows, const int32_t* strip_rows2);
+
 /* Adjoint of one time step (the reverse of streaming, collision, force, wetting and psi, in that order).
  * Given the FP64 populations f_n of step n (d_state_n, [9][ny-2][nx], unshifted) and the adjoint
  * lambda_{n+1} = dL/df_{n+1} (same layout), writes lambda_n = (d f_{n+1} / d f_n)^T lambda_{n+1} to d_lambda_n

@@ -29,6 +29,10 @@ class Diag(C.Structure):
                 ("ghost_clamps", C.c_int64), ("steps", C.c_int64)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("two_step", C.c_int32), ("waves", C.c_int32), ("prefetch", C.c_int32), ("waves2", C.c_int32)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"liblbm error {code}: {msg}")
@@ -71,6 +75,8 @@ _SIGS = {
                                            C.c_void_p]),
     "lbm_measure_contact_angle_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                                     C.POINTER(C.c_int32), C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbm_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(Tuning), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lbm_last_error": (C.c_char_p, []),
 }
 

@@ -1290,6 +1290,47 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
   return LBM_OK;
 }
 
+int lbm_get_tuning(const lbm_ctx* c, lbm_tuning* t, int32_t* strip_rows, int32_t* strip_rows2) {
+  if (!c || !t) return fail(LBM_E_INVALID, "NULL argument");
+  t->two_step = c->step2 ? 1 : 0;
+  t->waves = c->waves;
+  t->prefetch = c->prefetch ? 1 : 0;
+  t->waves2 = c->waves2;
+  for (int i = 0; i < c->n(); ++i) {
+    if (strip_rows) strip_rows[i] = c->inst[i].strip_rows;
+    if (strip_rows2) strip_rows2[i] = c->inst[i].strip_rows2;
+  }
+  return LBM_OK;
+}
+
+int lbm_set_tuning(lbm_ctx* c, const lbm_tuning* t, const int32_t* strip_rows, const int32_t* strip_rows2) {
+  if (!c || !t) return fail(LBM_E_INVALID, "NULL argument");
+  auto wave_ok = [](int w) {
+    for (int k = 0; k < kNumWaveChoices; ++k)
+      if (kWaveChoices[k] == w) return true;
+    return false;
+  };
+  if (!wave_ok(t->waves) || !wave_ok(t->waves2)) return fail(LBM_E_INVALID, "wavefronts per block not in {1,2,4,8}");
+  if ((t->prefetch != 0 && t->prefetch != 1) || (t->two_step != 0 && t->two_step != 1))
+    return fail(LBM_E_INVALID, "prefetch and two_step must be 0 or 1");
+  for (int i = 0; i < c->n(); ++i)
+    if ((strip_rows && strip_rows[i] < 1) || (strip_rows2 && strip_rows2[i] < 1))
+      return fail(LBM_E_INVALID, "instance %d: rows per strip must be >= 1", i);
+  c->waves = t->waves;
+  c->prefetch = t->prefetch != 0;
+  c->waves2 = t->waves2;
+  c->step2 = t->two_step != 0 && c->f32();
+  for (int i = 0; i < c->n(); ++i) {
+    if (strip_rows) c->inst[i].strip_rows = strip_rows[i];
+    if (strip_rows2) c->inst[i].strip_rows2 = strip_rows2[i];
+  }
+  c->build_tasks();
+  const int rc = c->upload_tables();
+  if (rc != LBM_OK) return rc;
+  c->drop_graphs();
+  return LBM_OK;
+}
+
 }  // extern "C"
 
 namespace {

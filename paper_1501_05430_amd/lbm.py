@@ -1,7 +1,9 @@
 """Python front end of liblbm: torch owns the device workspace and the stream; every step of the method runs in
 the library's HIP kernels. Argument marshalling only."""
 import ctypes as C
+import json
 import math
+import os
 
 import numpy as np
 
@@ -181,10 +183,70 @@ class LBM:
         check(rc)
         return ms.value
 
-    def autotune(self, inst=0, trial_steps=20):
+    def autotune(self, inst=0, trial_steps=20, cache=None):
+        """lbm_autotune on instance inst (-1: all of them); returns the chosen rows per strip. With cache (a JSON
+        file path), a shape recorded there for the same device, library and instances is applied without the
+        trials, and a new search's result is recorded (the file is replaced atomically)."""
+        key = self._tuning_key(inst, trial_steps) if cache is not None else None
+        if key is not None and os.path.exists(cache):
+            with open(cache) as f:
+                rec = json.load(f).get(key)
+            if rec is not None:
+                self.set_tuning(rec)
+                i0 = max(inst, 0)
+                return rec["strip_rows2" if rec["two_step"] and self._two_step_applies(inst) else "strip_rows"][i0]
         out = C.c_int32()
         check(self.lib.lbm_autotune(self.ctx, inst, int(trial_steps), C.byref(out)))
+        if key is not None:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[key] = self.tuning()
+            tmp = f"{cache}.{os.getpid()}.tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
         return out.value
+
+    def tuning(self):
+        """The step shape (lbm_get_tuning): two_step, waves, prefetch, waves2 and each instance's rows per strip."""
+        n = len(self.params)
+        t = _lib.Tuning()
+        rows, rows2 = (C.c_int32 * n)(), (C.c_int32 * n)()
+        check(self.lib.lbm_get_tuning(self.ctx, C.byref(t), rows, rows2))
+        return {"two_step": t.two_step, "waves": t.waves, "prefetch": t.prefetch, "waves2": t.waves2,
+                "strip_rows": list(rows), "strip_rows2": list(rows2)}
+
+    def set_tuning(self, rec):
+        """Apply a shape from tuning() (lbm_set_tuning); results do not depend on it."""
+        n = len(self.params)
+        if len(rec["strip_rows"]) != n or len(rec["strip_rows2"]) != n:
+            raise ValueError(f"tuning record for {len(rec['strip_rows'])} instances, context has {n}")
+        t = _lib.Tuning(int(rec["two_step"]), int(rec["waves"]), int(rec["prefetch"]), int(rec["waves2"]))
+        rows = (C.c_int32 * n)(*[int(v) for v in rec["strip_rows"]])
+        rows2 = (C.c_int32 * n)(*[int(v) for v in rec["strip_rows2"]])
+        check(self.lib.lbm_set_tuning(self.ctx, C.byref(t), rows, rows2))
+
+    def _two_step_applies(self, inst):
+        sel = self.params if inst < 0 else [self.params[inst]]
+        return all(p.precision != _lib.LBM_F64 and p.tau == 1.0 and p.boundary == 0 and not any(p.mrt_rates)
+                   and p.kappa == 0.0 for p in sel)
+
+    def _tuning_key(self, inst, trial_steps):
+        """Device, library build and everything about the instances that decides a launch's time."""
+        import hashlib
+        import torch
+        props = torch.cuda.get_device_properties(self.device)
+        h = hashlib.sha256()
+        with open(_lib.LIB_PATH, "rb") as f:
+            h.update(f.read())
+        fields = [f for f, _ in _lib.Params._fields_]
+        inst_desc = [[list(v) if hasattr(v, "__len__") else v for v in (getattr(p, f) for f in fields)]
+                     for p in self.params]
+        desc = json.dumps({"device": props.name, "cus": props.multi_processor_count, "lib": h.hexdigest()[:16],
+                           "inst": inst, "trial_steps": int(trial_steps), "params": inst_desc}, sort_keys=True)
+        return hashlib.sha256(desc.encode()).hexdigest()[:24]
 
     # ------------------------------------------------------------------------------------------- readout
     def mass(self, inst=0):

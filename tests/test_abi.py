@@ -37,6 +37,11 @@ def test_binding_declares_every_entry_point():
     assert set(declared_functions()) == set(_lib._SIGS)
 
 
+def test_tuning_struct_matches_header():
+    from paper_1501_05430_amd import _lib
+    assert C.sizeof(_lib.Tuning) == 4 * 4 and _lib.Tuning.waves2.offset == 12
+
+
 def test_params_struct_matches_header_size():
     # lbm_params: 10 int32 + 22 double = 216 bytes, no padding
     from paper_1501_05430_amd import _lib

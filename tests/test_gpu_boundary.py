@@ -121,3 +121,73 @@ def test_rollout_gradient_unchanged_by_the_library_seed():
     tbar = theta_bar.cpu()
     assert torch.equal(tb.grad, tbar[0]) and torch.equal(tt.grad, tbar[1])
     sim.close()
+
+
+def _batch(precision="f32_shifted"):
+    import paper_1501_05430_amd as P
+    rng = np.random.default_rng(21)
+    cases = []
+    for k, (nx, ny) in enumerate([(128, 64), (256, 128), (64, 32), (256, 128)]):
+        th = math.radians(rng.uniform(40, 140))
+        cases.append(W.Case(f"t{k}", nx, ny, 0.75, np.full(nx, th), np.full(nx, math.pi / 2), [nx / 2],
+                            [W.wall_cap_centre(0.3 * ny, th)], [0.3 * ny], 0))
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision=precision, **P.fp32_options(c.T_over_Tc, precision))
+              for c in cases]
+    sim = P.LBM(params)
+    for i, c in enumerate(cases):
+        sim.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
+        sim.init_droplet(c.xc, c.yc, c.R, inst=i)
+    return sim
+
+
+def test_autotune_cache_records_and_reapplies_the_shape(tmp_path):
+    """lbm_autotune's choice is kept in a JSON cache (the binding's autotune(cache=...)): a second context with the
+    same instances applies the recorded shape without the trials (lbm_set_tuning), gets the same rows per strip,
+    and steps to the same state bit for bit as the tuned context and as an untuned one."""
+    import json
+    import time
+    path = str(tmp_path / "tuning.json")
+    a = _batch()
+    t0 = time.perf_counter()
+    chosen = a.autotune(inst=-1, trial_steps=4, cache=path)
+    t_search = time.perf_counter() - t0
+    rec = a.tuning()
+    data = json.load(open(path))
+    assert len(data) == 1 and list(data.values())[0] == rec
+    b = _batch()
+    t0 = time.perf_counter()
+    assert b.autotune(inst=-1, trial_steps=4, cache=path) == chosen
+    t_cached = time.perf_counter() - t0
+    assert b.tuning() == rec
+    c = _batch()                         # library defaults
+    for s in (a, b, c):
+        s.step(37, inst=-1)
+    for i in range(4):
+        pa = a.populations(inst=i)
+        assert np.array_equal(pa, b.populations(inst=i)) and np.array_equal(pa, c.populations(inst=i)), i
+    print(f"\n  search {t_search:.2f} s, from the cache {t_cached:.3f} s; shape {rec}")
+    assert t_cached < t_search
+    for s in (a, b, c):
+        s.close()
+
+
+def test_set_tuning_rejects_bad_shapes_and_changes_nothing():
+    import paper_1501_05430_amd as P
+    sim = _batch()
+    rec = sim.tuning()
+    for bad in (dict(waves=3), dict(waves2=16), dict(prefetch=2), dict(two_step=-1),
+                dict(strip_rows=[0, 8, 8, 8]), dict(strip_rows2=[8, 8, -1, 8])):
+        with pytest.raises(P.LbmError) as e:
+            sim.set_tuning(dict(rec, **bad))
+        assert e.value.code == 1
+        assert sim.tuning() == rec
+    # a valid other shape: one-step launches with two wavefronts, 5-row strips; the state still steps bitwise alike
+    ref = _batch()
+    sim.set_tuning(dict(rec, two_step=0, waves=2, prefetch=1, strip_rows=[5, 5, 5, 5]))
+    assert sim.tuning()["waves"] == 2 and sim.tuning()["two_step"] == 0
+    sim.step(21, inst=-1)
+    ref.step(21, inst=-1)
+    for i in range(4):
+        assert np.array_equal(sim.populations(inst=i), ref.populations(inst=i)), i
+    sim.close()
+    ref.close()
