@@ -517,7 +517,9 @@ def main():
         sim64.close()
         out["extras"] = {
             "fp64_same_lattice": {"mlups": round(nodes * 1000 / ms64 / 1e3, 1),
-                                  "gbs_alg": round(144 * nodes * 1000 / ms64 / 1e6, 1), "stable": st64},
+                                  "gbs_alg": round(144 * nodes * 1000 / ms64 / 1e6, 1),
+                                  "frac_of_hbm_peak": round(144 * nodes * 1000 / ms64 / 1e6 / PEAK_HBM_GBS, 4),
+                                  "stable": st64},
             "f32_shifted_mixed_same_lattice": mixed_rate(case),
             "batched_256": batched_vs_plain(),
             "adjoint_fp64_same_lattice": adjoint_rate(case),

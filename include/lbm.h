@@ -100,9 +100,10 @@ typedef struct {
   int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step (any precision) */
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects the one-step kernel with 1, 2, 4 or 8 wavefronts
                              (64, 128, 256 or 512 aligned columns) per block, 5..8 the same with the next row's
-                             loads in flight; 9..12 the two-step kernel (two time steps per launch, FP32, tau = 1
-                             BGK with geometric walls; other selections step one at a time) with 1, 2, 4 or 8
-                             wavefronts per block; 0 = library default (two-step for FP32 where it applies).
+                             loads in flight; 9..12 the two-step kernel (two time steps per launch, tau = 1 BGK
+                             with geometric walls, any precision; other selections step one at a time) with 1, 2,
+                             4 or 8 wavefronts per block; 0 = library default (two-step where it applies on
+                             contexts of at least 2^22 fluid nodes, one-step below).
                              Instance 0's value applies to the whole context (lbm_autotune may change it). Results
                              do not depend on it (bitwise). */
   int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y] */

@@ -228,6 +228,15 @@ constexpr int kMinDefaultStripRows = 2;
 constexpr int kDefaultWaves2 = 4;
 constexpr int kDefaultStripRows2 = 32;
 constexpr int kMinStripRows2 = 8, kMaxStripRows2 = 256;  // bounds of the default from the occupancy
+// FP64 storage: at most 24 output rows per strip. At two blocks per compute unit the FP64 kernel runs faster with
+// several rounds of 24-row strips than with one round of taller ones (4096 x 2048: 45.7 against 34.0 GLUPS); FP32
+// loses a quarter of its rate to a partial second round, so it keeps the one-round rule.
+constexpr int kMaxStripRows2F64 = 24;
+// Below about 4e6 fluid nodes per context the two-step kernel has too few tasks to pay for its halo: one-step
+// launches are as fast or faster (200 x 100: 1.8 against 1.2 GLUPS; 512 x 256: 10.3 against 7.7; 1024 x 512
+// equal; 2048 x 1024 equal), above it two steps per launch win (4096 x 2048: 89.6 against 65, FP64 45.8 against
+// 34.9).
+constexpr double kStep2MinNodes = 4194304.0;
 constexpr int kStep2Halo = 6;  // step A columns beyond a two-step tile's outputs (three per side)
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
@@ -469,9 +478,9 @@ struct lbm_ctx {
   }
 
   bool f32() const { return storage != STORE_F64; }
-  // the two-step kernel covers the selection: FP32 storage, tau = 1 BGK and geometric walls everywhere
+  // the two-step kernel covers the selection: tau = 1 BGK and geometric walls everywhere (any storage)
   bool step2_ok(int sel) const {
-    if (!step2 || !f32() || !tau1(sel)) return false;
+    if (!step2 || !tau1(sel)) return false;
     for (int i = 0; i < n(); ++i)
       if ((sel < 0 || i == sel) && inst[i].p.boundary != LBM_WALLS_Y) return false;
     return true;
@@ -591,15 +600,20 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     c->waves = kDefaultWaves64;
     c->prefetch = kDefaultPrefetch64;
   }
-  // two steps per launch by default for FP32 (where the selection allows it); variants 1..8 choose a one-step
-  // shape, 9..12 the two-step kernel with 1, 2, 4 or 8 wavefronts per block
-  c->step2 = c->f32();
+  // two steps per launch by default (where the selection allows it) on contexts of at least kStep2MinNodes fluid
+  // nodes; variants 1..8 choose a one-step shape, 9..12 the two-step kernel with 1, 2, 4 or 8 wavefronts per block
+  {
+    double nodes = 0;
+    for (int i = 0; i < n_inst; ++i) nodes += (double)p[i].nx * (p[i].ny - 2);
+    c->step2 = nodes >= kStep2MinNodes;
+  }
   if (p[0].step_variant > 0 && p[0].step_variant <= 2 * kNumWaveChoices) {
     c->waves = kWaveChoices[(p[0].step_variant - 1) % kNumWaveChoices];
     c->prefetch = (p[0].step_variant - 1) / kNumWaveChoices == 1;
     c->step2 = false;
   } else if (p[0].step_variant > 2 * kNumWaveChoices) {
     c->waves2 = kWaveChoices[p[0].step_variant - 2 * kNumWaveChoices - 1];
+    c->step2 = true;
   }
   c->inst.resize(n_inst);
   c->hdesc.resize(n_inst);
@@ -700,12 +714,13 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     // two-step kernel: one round of resident blocks over all instances, each task a tile of a strip; fewer, taller
     // strips than that leave compute units idle, more add a partial second round and more halo rows
     int per_cu = 0;
-    if (c->f32() && step2_blocks_per_cu(c->waves2, c->storage == STORE_F32M, &per_cu) == hipSuccess &&
+    if (step2_blocks_per_cu(c->waves2, c->storage, &per_cu) == hipSuccess &&
         per_cu > 0) {
       const int wmax = 64 * c->waves2 - kStep2Halo;
       double tile_rows = 0;
       for (int i = 0; i < n_inst; ++i) tile_rows += (double)((p[i].nx + wmax - 1) / wmax) * (p[i].ny - 2);
-      const int h2 = (int)std::max<long>(kMinStripRows2, std::min<long>(kMaxStripRows2,
+      const long hcap = c->storage == STORE_F64 ? kMaxStripRows2F64 : kMaxStripRows2;
+      const int h2 = (int)std::max<long>(kMinStripRows2, std::min<long>(hcap,
                                          (long)std::ceil(tile_rows / ((double)cus * per_cu))));
       for (int i = 0; i < n_inst; ++i)
         if (p[i].strip_rows <= 0) c->inst[i].strip_rows2 = h2;
@@ -859,7 +874,7 @@ int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check, int
     const bool chk = chk_at(i);
     if (two && !chk && i + 1 < count && !chk_at(i + 1)) {
       if (!dry)
-        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage == STORE_F32M,
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage,
                              (int)(nl & 1), c->stream));
       i += 2;
       continue;
@@ -1203,7 +1218,7 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
     for (int k = 0; k <= launches; ++k) {
       if (k == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // launch 0 warms up
       if (two)
-        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage == STORE_F32M, 0,
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage, 0,
                              c->stream));
       else
         HIP_TRY(launch_step(c->storage, false, c->tau1(inst), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a,
@@ -1262,7 +1277,7 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
     use2 = best2 < best;
     if (use2) best = best2;
   }
-  c->step2 = use2 || (c->f32() && guard.step2 && !c->step2_ok(inst));
+  c->step2 = use2 || (guard.step2 && !c->step2_ok(inst));
   // 2. with several shape classes, refine each class's strip height in turn (the others held)
   if (shapes.size() > 1) {
     for (auto& kv : shapes) {
@@ -1319,7 +1334,7 @@ int lbm_set_tuning(lbm_ctx* c, const lbm_tuning* t, const int32_t* strip_rows, c
   c->waves = t->waves;
   c->prefetch = t->prefetch != 0;
   c->waves2 = t->waves2;
-  c->step2 = t->two_step != 0 && c->f32();
+  c->step2 = t->two_step != 0;
   for (int i = 0; i < c->n(); ++i) {
     if (strip_rows) c->inst[i].strip_rows = strip_rows[i];
     if (strip_rows2) c->inst[i].strip_rows2 = strip_rows2[i];

@@ -20,6 +20,8 @@
 // Block order: consecutive tasks (tiles of one row band, then the next band) are given to the same XCD, so tiles
 // that share halo rows and boundary cache lines meet in one L2.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 
 #include "lbm_device.h"
@@ -30,12 +32,14 @@ namespace {
 
 constexpr int kXcds = 8;
 
-template <int W, bool MIX>
-__global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__ descs,
+// FP64: at least two blocks per compute unit, which caps the registers at 256 (two wavefronts per SIMD; the ring of
+// FP64 rows allows two blocks of four wavefronts per compute unit)
+template <class S, int W, bool MIX>
+__global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1)) void k_step2(const InstDesc* __restrict__ descs,
                                                     const WaveTask* __restrict__ tasks, int ntasks, int flip) {
-  typedef float C;
-  typedef float S;
+  typedef typename ComputeOf<S>::type C;
   typedef typename Gbl<S>::T GS;
+  static_assert(!MIX || std::is_same<S, float>::value, "the mixed arithmetic is a form of FP32 storage");
   constexpr int L = WAVE * W;
   // XCD-aware order: blocks go round-robin to the XCDs; XCD k takes the k-th contiguous share of the task table.
   const int per = (ntasks + kXcds - 1) / kXcds;
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
 
   // LDS: step A's post-collision rows (ring of 3 rows), row exchange buffers, step B's psi rows (ring of 3 rows,
   // ghost rows included) and step B's boundary-row densities (bottom, top) for its ghost rows.
-  __shared__ C gA[3][9][L];
+  __shared__ S gA[3][9][L];
   __shared__ C xa[2][L + 2];
   __shared__ C psB[3][L];
   __shared__ C rhB[2][L];
@@ -310,45 +314,47 @@ __global__ __launch_bounds__(WAVE * W) void k_step2(const InstDesc* __restrict__
   }
 }
 
-template <int W, bool MIX>
+template <class S, int W, bool MIX>
 int occupancy_of(int* blocks) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<W, MIX>, WAVE * W, 0);
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<S, W, MIX>, WAVE * W, 0);
 }
 
-template <bool MIX>
+template <class S, bool MIX>
 hipError_t blocks_per_cu(int waves, int* blocks) {
   switch (waves) {
-    case 1: return (hipError_t)occupancy_of<1, MIX>(blocks);
-    case 2: return (hipError_t)occupancy_of<2, MIX>(blocks);
-    case 4: return (hipError_t)occupancy_of<4, MIX>(blocks);
-    default: return (hipError_t)occupancy_of<8, MIX>(blocks);
+    case 1: return (hipError_t)occupancy_of<S, 1, MIX>(blocks);
+    case 2: return (hipError_t)occupancy_of<S, 2, MIX>(blocks);
+    case 4: return (hipError_t)occupancy_of<S, 4, MIX>(blocks);
+    default: return (hipError_t)occupancy_of<S, 8, MIX>(blocks);
   }
 }
 
-template <bool MIX>
+template <class S, bool MIX>
 void launch2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip, unsigned grid,
              hipStream_t s) {
   switch (waves) {
-    case 1: hipLaunchKernelGGL((k_step2<1, MIX>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 2: hipLaunchKernelGGL((k_step2<2, MIX>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 4: hipLaunchKernelGGL((k_step2<4, MIX>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    default: hipLaunchKernelGGL((k_step2<8, MIX>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 1: hipLaunchKernelGGL((k_step2<S, 1, MIX>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 2: hipLaunchKernelGGL((k_step2<S, 2, MIX>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 4: hipLaunchKernelGGL((k_step2<S, 4, MIX>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    default: hipLaunchKernelGGL((k_step2<S, 8, MIX>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
   }
 }
 
 }  // namespace
 
-hipError_t step2_blocks_per_cu(int waves, bool mix, int* blocks) {
+hipError_t step2_blocks_per_cu(int waves, int storage, int* blocks) {
   *blocks = 0;
-  return mix ? blocks_per_cu<true>(waves, blocks) : blocks_per_cu<false>(waves, blocks);
+  if (storage == STORE_F64) return blocks_per_cu<double, false>(waves, blocks);
+  return storage == STORE_F32M ? blocks_per_cu<float, true>(waves, blocks) : blocks_per_cu<float, false>(waves, blocks);
 }
 
-hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, bool mix, int flip,
+hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage, int flip,
                         hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(((ntasks + kXcds - 1) / kXcds) * kXcds);
-  if (mix) launch2<true>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
-  else launch2<false>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  if (storage == STORE_F64) launch2<double, false>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  else if (storage == STORE_F32M) launch2<float, true>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  else launch2<float, false>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
   return hipGetLastError();
 }
 

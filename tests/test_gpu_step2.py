@@ -1,5 +1,5 @@
-"""The two-step kernel (two time steps per launch, lbm_step2.hip) against one-step launches, bit for bit, and
-against the FP64 reference, through the C-ABI. It runs the same per-node arithmetic, so every population must
+"""The two-step kernel (two time steps per launch, lbm_step2.hip) against one-step launches, bit for bit in every
+precision, and against the FP64 reference, through the C-ABI. It runs the same per-node arithmetic, so every population must
 match exactly: across lattice shapes (ragged tiles, lattices narrower than a tile, the fewest rows), block shapes,
 strip heights, odd and even step counts, both EOS, the force and wetting options, checked steps in between and the
 batched form."""
@@ -35,7 +35,7 @@ def pair(case, steps, variant2, precision="f32_shifted", strip_rows=0, check_eve
     return a, b, d1, d2
 
 
-@pytest.mark.parametrize("precision", ["f32_shifted", "f32_shifted_mixed"])
+@pytest.mark.parametrize("precision", ["f32_shifted", "f32_shifted_mixed", "f64"])
 @pytest.mark.parametrize("nx,ny,steps,variant,rows", [
     (300, 80, 40, 11, 0),     # two tiles of 4 wavefronts, default strips
     (300, 80, 41, 11, 7),     # odd step count: the last step is a one-step launch
@@ -57,7 +57,7 @@ def test_two_step_equals_one_step_bitwise(nx, ny, steps, variant, rows, precisio
     assert np.array_equal(a, b), np.abs(a - b).max()
 
 
-@pytest.mark.parametrize("precision", ["f32", "f32_shifted", "f32_shifted_mixed"])
+@pytest.mark.parametrize("precision", ["f32", "f32_shifted", "f32_shifted_mixed", "f64"])
 @pytest.mark.parametrize("kw", [dict(A=0.0, wet_iters=0), dict(wet_iters=7, A=-0.3), dict(body_force=(1e-6, -2e-6)),
                                 dict(piecewise=PW100), dict(wet_iters=1)])
 def test_two_step_options_bitwise(precision, kw):
@@ -100,7 +100,7 @@ def test_checked_steps_between_two_step_launches(check_every):
 def test_graph_chunks_and_remainders_bitwise():
     case = case_of(180, 50, 0.75, 70.0, 95.0, [(90, 0.5, 18.0)])
     one = gpu_sim(case, precision="f32_shifted", step_variant=5, check_every=10)
-    two = gpu_sim(case, precision="f32_shifted", check_every=10)  # library default: two-step for FP32
+    two = gpu_sim(case, precision="f32_shifted", check_every=10, step_variant=11)
     for n in (1, 7, 20, 33, 64, 2):
         one.step(n)
         two.step(n)
@@ -159,7 +159,7 @@ def test_two_step_fp32_vs_reference(steps):
     sim.close()
 
 
-@pytest.mark.parametrize("precision", ["f32_shifted", "f32_shifted_mixed"])
+@pytest.mark.parametrize("precision", ["f32_shifted", "f32_shifted_mixed", "f64"])
 def test_two_step_equals_one_step_over_a_long_run(precision):
     """The 1024 x 512 droplet at 90 deg (T = 0.7 T_c, R = 120) over 4000 steps: two-step and one-step launches agree
     bit for bit at every 1000 steps (each kernel inlines the same node arithmetic, whose rounding is spelled out)."""
