@@ -32,23 +32,29 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")
 TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step2_f32_batched_c4.json")
 TRAFFIC_FILE_MIXED = os.path.join(ROOT, "profiles", "traffic_step2_mixed_c3.json")
+TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "traffic_step2_f64_c3.json")
 
 
 # HBM-traffic summaries of the step kernel (profiles/traffic_<name>.json), made from two rocprofv3 counter runs of
 # this script (FETCH_SIZE, then WRITE_SIZE) by `bench.py --traffic-summary <name>`
 TRAFFIC_SPECS = {
     "step2_f32_c3": dict(
-        match="k_step2<4, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        match="k_step2<float, 4, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<W=4> (two time steps per launch; FP32 storage shifted by rho_v, FP32 arithmetic with the FP64 "
              "EOS in the vapour, tau = 1 BGK, geometric walls), 4096x2048 lattice, T = 0.5 T_c, theta = 45 deg, "
              "65 droplets; default shape"),
     "step2_mixed_c3": dict(
-        match="k_step2<4, true>", workload="c3",
+        match="k_step2<float, 4, true>", workload="c3",
         args="--precision f32_shifted_mixed --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<W=4> in the mixed form (FP32 storage shifted by rho_v and FP32 sums; psi, force, equilibrium "
              "and forcing in FP64), same lattice and shape"),
+    "step2_f64_c3": dict(
+        match="k_step2<double, 4, false>", workload="c3", bytes_per_update=144,
+        args="--precision f64 --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        desc="k_step2<double, W=4> (two time steps per launch in FP64: storage and arithmetic), same lattice; "
+             "strips of at most 24 output rows"),
     "step2_f32_batched_c4": dict(
-        match="k_step2<", exclude=", true>", workload="c4", args="--batched-only --steps 40",
+        match="k_step2<float, ", exclude=", true>", workload="c4", args="--batched-only --steps 40",
         desc="k_step2 (two time steps per launch, the autotuner's block shape) over the 256-instance batch (sizes "
              "64x32 .. 512x256, T/T_c in [0.6, 0.9], theta in [20, 160] deg, seed 1501), FP32 shifted by rho_v"),
 }
@@ -76,7 +82,7 @@ def traffic_summary(name):
         case = W.c3_large()
         nodes = case.fluid_nodes
         pitch = (case.nx + 63) // 64 * 64
-        state_bytes = 4 * 9 * (case.ny - 2) * pitch
+        state_bytes = 4 * 9 * (case.ny - 2) * pitch   # the probe's copy is of the FP32 state
     else:
         nodes = sum(c.fluid_nodes for c in W.c4_batch())
         state_bytes = None
@@ -92,7 +98,7 @@ def traffic_summary(name):
         calib["kernel"] += " (taken from the step2_f32_c3 run)"
     rd = runs["FETCH_SIZE"][0] * 1024 * calib["fetch_scale"]
     wr = runs["WRITE_SIZE"][0] * 1024 * calib["write_scale"]
-    alg = 2 * 72 * nodes
+    alg = 2 * spec.get("bytes_per_update", 72) * nodes
     out = {
         "kernel": spec["desc"],
         "kernel_source_sha256": kernel_sha(),
@@ -428,8 +434,9 @@ def main():
                     help="run only the 256-instance batched leg and print its JSON (for profiling that launch)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint legs on the headline lattice and print their JSON (for profiling)")
-    ap.add_argument("--precision", default="f32_shifted", choices=["f32_shifted", "f32_shifted_mixed"],
-                    help="the timed form: FP32 arithmetic (default) or the mixed form (FP64 force and equilibrium)")
+    ap.add_argument("--precision", default="f32_shifted", choices=["f32_shifted", "f32_shifted_mixed", "f64"],
+                    help="the timed form: FP32 arithmetic (default), the mixed form (FP64 force and equilibrium) "
+                         "or FP64")
     ap.add_argument("--traffic-summary", metavar="NAME", choices=sorted(TRAFFIC_SPECS),
                     help="write profiles/traffic_NAME.json from the two counter runs under gpurun_out/ and exit")
     args = ap.parse_args()
@@ -473,7 +480,11 @@ def main():
     achieved = bytes_alg / (ms_step * 1e-3) / 1e9
 
     mixed = args.precision == "f32_shifted_mixed"
-    traffic, per_launch = profile_traffic(TRAFFIC_FILE_MIXED if mixed else TRAFFIC_FILE)
+    f64 = args.precision == "f64"
+    if f64:
+        bytes_alg = 144 * nodes  # 9 FP64 populations read + 9 written per fluid node and step
+        achieved = bytes_alg / (ms_step * 1e-3) / 1e9
+    traffic, per_launch = profile_traffic(TRAFFIC_FILE_F64 if f64 else (TRAFFIC_FILE_MIXED if mixed else TRAFFIC_FILE))
 
     out = {
         "metric": "MLUPS & % HBM roofline; FP32/batched/adjoint vs plain FP64 at stated error",
@@ -486,12 +497,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if mixed else "f32",
+        "dtype": "f64" if f64 else ("f32+f64" if mixed else "f32"),
         "data": "synthetic",
         "config": {
             "workload": case.name, "nx": case.nx, "ny": case.ny, "fluid_nodes": nodes, "T_over_Tc": 0.5,
-            "theta_deg": 45, "droplets": len(case.xc), "seed": W.SEED, "precision": ("f32_shifted_mixed (rho0 = rho_v; FP32 storage and sums, FP64 psi, force and "
-                                                          "equilibrium)" if mixed else
+            "theta_deg": 45, "droplets": len(case.xc), "seed": W.SEED, "precision": ("f64" if f64 else
+                                                          "f32_shifted_mixed (rho0 = rho_v; FP32 storage and sums, FP64 "
+                                                          "psi, force and equilibrium)" if mixed else
                                                           "f32_shifted (rho0 = rho_v; FP64 EOS in vapour)"),
             "check_every": 100, "stable": stable, "mass_at_last_check": diag["mass"],
             "measured_theta_deg": round(math.degrees(theta[0]), 3),
@@ -501,7 +513,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
             # current), traffic_gbs those bytes over this run's time per launch
-            "kernel": f"k_step2<4, {'true' if mixed else 'false'}> (two time steps per launch)", "steps_per_launch": 2,
+            "kernel": f"k_step2<{'double' if f64 else 'float'}, 4, {'true' if mixed else 'false'}> (two time steps "
+                      "per launch)", "steps_per_launch": 2,
             "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic
