@@ -102,7 +102,9 @@ __device__ inline double sqrt64_for_f32(double x) {
   return fma(s, fma(-s, h, 0.5), s);
 }
 
-// psi of an FP32 density from the FP64 EOS (refined hardware reciprocal and square root), rounded to FP32.
+// psi of an FP32 density from the FP64 EOS, rounded to FP32. FULL: reciprocal and square root refined to about
+// 1 ulp of FP64 (the mixed form, whose long-run accuracy spends that margin); otherwise once (the FP32 form).
+template <bool FULL>
 __device__ inline float psi_f32_via64(const InstDesc& d, float rho, bool& clamped) {
 #pragma clang fp contract(off)
   const double r = (double)rho;
@@ -114,11 +116,11 @@ __device__ inline float psi_f32_via64(const InstDesc& d, float rho, bool& clampe
     const double eta = d.eos_b4 * r;
     const double om = 1.0 - eta;
     const double poly = fmac(eta, fmac(eta, 1.0 - eta, 1.0), 1.0);
-    p = fmac(r * d.RT * poly, rcp64_for_f32(om * om * om), -(d.eos_a * r) * r);
+    p = fmac(r * d.RT * poly, FULL ? rcp64(om * om * om) : rcp64_for_f32(om * om * om), -(d.eos_a * r) * r);
   }
   const double arg = d.two_over_Gpsi * fmac(r, -1.0 / 3.0, p);
   clamped = arg < 0.0;
-  return (float)sqrt64_for_f32(arg);
+  return (float)(FULL ? sqrt64(arg) : sqrt64_for_f32(arg));
 }
 
 // FP32 modes: below rho_fp64_below the EOS is evaluated in FP64 (vapour side of a large density ratio),
@@ -126,7 +128,7 @@ __device__ inline float psi_f32_via64(const InstDesc& d, float rho, bool& clampe
 __device__ inline float psi_f32(const InstDesc& d, float rho, bool& clamped) {
 #pragma clang fp contract(off)
   const bool pw = d.eos_kind == 1;
-  if (rho < (float)d.rho_fp64_below) return psi_f32_via64(d, rho, clamped);
+  if (rho < (float)d.rho_fp64_below) return psi_f32_via64<false>(d, rho, clamped);
   float p;
   if (pw) {
     p = pw_pressure(d, rho);
@@ -183,7 +185,7 @@ __device__ inline void hybrid_force(const InstDesc& d, T pc, T pcL, T pcR, T pm,
 // rho_fp64_below); LBM_F32_SHIFTED_MIXED (MIX) always in FP64, rounded to FP32.
 template <bool MIX, class C>
 __device__ inline C node_psi(const InstDesc& d, C rho, bool& cl) {
-  if constexpr (MIX) return psi_f32_via64(d, rho, cl);
+  if constexpr (MIX) return psi_f32_via64<true>(d, rho, cl);
   else return psi_eval(d, rho, cl);
 }
 
