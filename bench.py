@@ -82,16 +82,17 @@ def traffic_summary(name):
         case = W.c3_large()
         nodes = case.fluid_nodes
         pitch = (case.nx + 63) // 64 * 64
-        state_bytes = 4 * 9 * (case.ny - 2) * pitch   # the probe's copy is of the FP32 state
+        copy_bytes = 4 * 9 * (case.ny - 2) * pitch    # the probe copies an FP32 state of this lattice
+        state_bytes = spec.get("bytes_per_update", 72) // 18 * 9 * (case.ny - 2) * pitch   # the kernel's own state
     else:
         nodes = sum(c.fluid_nodes for c in W.c4_batch())
-        state_bytes = None
-    if runs["FETCH_SIZE"][2] is not None and state_bytes:
-        calib = {"kernel": f"{COPY_KERNEL} of the bench's bandwidth_ceilings (bw_probe.hip), {state_bytes:,} bytes "
+        copy_bytes = state_bytes = None
+    if runs["FETCH_SIZE"][2] is not None and copy_bytes:
+        calib = {"kernel": f"{COPY_KERNEL} of the bench's bandwidth_ceilings (bw_probe.hip), {copy_bytes:,} bytes "
                            "copied per dispatch",
                  "fetch_kib": round(runs["FETCH_SIZE"][2], 3), "write_kib": round(runs["WRITE_SIZE"][2], 3),
-                 "fetch_scale": round(state_bytes / (1024 * runs["FETCH_SIZE"][2]), 4),
-                 "write_scale": round(state_bytes / (1024 * runs["WRITE_SIZE"][2]), 4)}
+                 "fetch_scale": round(copy_bytes / (1024 * runs["FETCH_SIZE"][2]), 4),
+                 "write_scale": round(copy_bytes / (1024 * runs["WRITE_SIZE"][2]), 4)}
     else:
         with open(os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")) as f:
             calib = dict(json.load(f)["calibration"])
