@@ -720,8 +720,16 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
       double tile_rows = 0;
       for (int i = 0; i < n_inst; ++i) tile_rows += (double)((p[i].nx + wmax - 1) / wmax) * (p[i].ny - 2);
       const long hcap = c->storage == STORE_F64 ? kMaxStripRows2F64 : kMaxStripRows2;
-      const int h2 = (int)std::max<long>(kMinStripRows2, std::min<long>(hcap,
-                                         (long)std::ceil(tile_rows / ((double)cus * per_cu))));
+      int h2 = (int)std::max<long>(kMinStripRows2, std::min<long>(hcap,
+                                   (long)std::ceil(tile_rows / ((double)cus * per_cu))));
+      // whole strips per instance can add tasks beyond one round: raise the height until they fit
+      auto ntasks2 = [&](int h) {
+        double n = 0;
+        for (int i = 0; i < n_inst; ++i)
+          n += (double)((p[i].nx + wmax - 1) / wmax) * (double)((p[i].ny - 2 + h - 1) / h);
+        return n;
+      };
+      while (h2 < hcap && ntasks2(h2) > (double)cus * per_cu) ++h2;
       for (int i = 0; i < n_inst; ++i)
         if (p[i].strip_rows <= 0) c->inst[i].strip_rows2 = h2;
     }

@@ -1,7 +1,7 @@
-// Two time steps per launch (temporal blocking) for the FP32 step with tau = 1 BGK-Guo collision and the geometric
-// walls of Sec. 4: the headline form of the method. Per lattice update it moves about half the HBM bytes of the
-// one-step kernel (lbm_kernels.hip), whose per-node arithmetic it repeats exactly: the results are bit for bit
-// those of two one-step launches.
+// Two time steps per launch (temporal blocking) for the step with tau = 1 BGK-Guo collision and the geometric walls
+// of Sec. 4 (the headline form of the method), in every storage precision. Per lattice update it moves about half
+// the HBM bytes of the one-step kernel (lbm_kernels.hip), whose per-node arithmetic it repeats exactly: the results
+// are bit for bit those of two one-step launches.
 //
 // A block of W wavefronts owns a tile: output columns [x0, x0 + bw) (bw <= 64 W - 6) of output rows [y0, ylast].
 // Lane l works on column x0 - 3 + l (periodic), so the tile carries three halo columns on each side.
@@ -17,6 +17,8 @@
 // further, so step B's outputs need step A on three more columns per side; step A's own halo (two columns) is
 // gathered by its edge lanes as in the one-step kernel. In y a strip reads g^t rows y0 - 4 .. ylast + 4.
 // Per launch and output node: 36 B read (plus the halo share) and 36 B written for two updates.
+// Latency: the rows of g^t (and the edge lanes' halo column) are loaded one row ahead of their use; the row loop is
+// unrolled by the three-row period of the window, so sliding it renames registers instead of copying them.
 // Block order: consecutive tasks (tiles of one row band, then the next band) are given to the same XCD, so tiles
 // that share halo rows and boundary cache lines meet in one L2.
 #include <hip/hip_runtime.h>
@@ -169,14 +171,13 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   const int ya0 = y0 - 2 >= 1 ? y0 - 2 : 1, ya1 = ylast + 2 <= ny - 2 ? ylast + 2 : ny - 2;
   const bool wall_start = ya0 == 1, wall_end = ya1 == ny - 2;
 
-  C tg = (C)0, tgL = (C)0, tgR = (C)0;  // step A's top ghost row (psi with neighbours), computed up front
+  C tg = (C)0, thg = (C)0;  // step A's top ghost row: psi on the lanes and on the edge lanes' halo columns
   if (wall_end) {
-    C f1[9], f2[9], r1, r2, h1, h2, p1, p2, hp1, hp2, g_rho, hg;
+    C f1[9], f2[9], r1, r2, h1, h2, p1, p2, hp1, hp2, g_rho;
     bool dm;
     produce(ny - 2, f1, r1, p1, h1, hp1, dm);
     produce(ny - 3, f2, r2, p2, h2, hp2, dm);
-    ghostA(1, ny - 2, r1, r2, h1, h2, g_rho, tg, hg);
-    xchg(tg, hg, tgL, tgR);
+    ghostA(1, ny - 2, r1, r2, h1, h2, g_rho, tg, thg);
   }
   // window: rows (b, c, a) = (y - 1, y, y + 1) when step A processes row y
   C fc[9], fn[9], fp[9];
@@ -199,13 +200,24 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
     if (ya0 + 1 <= ny - 2) {
       xchg(pa, hpa, paL, paR);
     } else {
-      pa = tg; paL = tgL; paR = tgR;
+      pa = tg;
+      xchg(tg, thg, paL, paR);
     }
   }
   // rows gathered by step A: ya0 - 1 .. ya1 + 1 within the fluid rows; the populations of row y + 2 are in flight
   // while row y is processed
   const int yread = ya1 + 1 <= ny - 2 ? ya1 + 1 : ny - 2;
-  if (act && ya0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ya0 + 2, fp);
+  // every lane loads (a lane past the tile's columns reads a valid column and its results are never stored), so the
+  // window slides by renaming registers
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fp[i] = (C)0;
+  if (ya0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ya0 + 2, fp);
+  // the halo column of the edge lanes, prefetched like fp by every lane of the waves that hold an edge lane
+  const bool wedge = wv == 0 || wv == (bwA - 1) / WAVE;
+  C hp[9], hn[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) hp[i] = (C)0;
+  if (wedge && ya0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ya0 + 2, hp);
 
   // ---------------------------------------------------------------------------------------------- step B state
   const bool wallB_bot = y0 == 1, wallB_top = ylast == ny - 2;
@@ -215,52 +227,51 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
 #pragma unroll
   for (int i = 0; i < 9; ++i) fBp[i] = (C)0;
 
-  // Iteration y: step A collides row y; step B gathers row y - 1 and collides row y - 2.
+  // Iteration y: step A collides row y; step B gathers row j = y - 1 and collides row m = y - 2. The window slides
+  // every iteration (past step A's last row nothing reads it), and the loop is unrolled by its period of three rows,
+  // so the slide is a renaming of registers rather than copies.
   const int yend = ylast + 2;
-  for (int y = ya0;; ++y) {
+  auto row = [&](const int y) -> bool {
     // ---- step A: collide row y into the ring, then bring row y + 2 into the window
-    bool slid = false;
-    if (y <= ya1) {
-      if (act) {
-        C fs[9];
-        force_collide(fc, rc, pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, fs);
-        const int s = y % 3;
+    if (y <= ya1 && act) {
+      C fs[9];
+      force_collide(fc, rc, pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, fs);
+      const int s = y % 3;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) gA[s][i][lx] = fs[i];
-      }
-      if (y < ya1) {
-        rb = rc; pb = pc; pbL = pcL; pbR = pcR;
-        rc = ra; pc = pa; pcL = paL; pcR = paR;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) fc[i] = fn[i];
-        const int ynew = y + 2;
-        if (ynew <= ny - 2) {
-          C g[9];
-#pragma unroll
-          for (int i = 0; i < 9; ++i) fn[i] = act ? fp[i] : (C)0;
-          if (act && ynew + 1 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + 1, fp);
-          if (edge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew, g);
-          bool dm;
-          ra = rho0 + sum9(fn);
-          pa = node_psi<MIX>(d, ra, dm);
-          C hpa = (C)0;
-          if (edge) hpa = node_psi<MIX>(d, rho0 + sum9(g), dm);
-          xput(pa, hpa);
-          slid = true;
-        } else {
-          pa = tg; paL = tgL; paR = tgR;
-        }
-      }
+      for (int i = 0; i < 9; ++i) gA[s][i][lx] = fs[i];
     }
+    rb = rc; pb = pc; pbL = pcL; pbR = pcR;
+    rc = ra; pc = pa;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { fc[i] = fn[i]; fn[i] = fp[i]; hn[i] = hp[i]; }
+    const int ynew = y + 2;
+    if (y < ya1 && ynew <= ny - 2) {
+      // densities of the rows prefetched an iteration ago, then the next prefetch
+      ra = rho0 + sum9(fn);
+      const C hra = rho0 + sum9(hn);
+      if (ynew + 1 <= yread) {
+        gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + 1, fp);
+        if (wedge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew + 1, hp);
+      }
+      bool dm;
+      pa = node_psi<MIX>(d, ra, dm);
+      C hpa = (C)0;
+      if (edge) hpa = node_psi<MIX>(d, hra, dm);
+      xput(pa, hpa);
+    } else {
+      // the row above the top fluid row is the ghost row (or step A is done and the window is no longer read)
+      ra = (C)0;
+      pa = tg;
+      xput(tg, thg);
+    }
+    pcL = paL; pcR = paR;
     __syncthreads();  // step A's row y is in the ring; the psi of row y + 2 is in xa
-    if (slid) xget(paL, paR);
+    xget(paL, paR);
 
     // ---- step B: gather row j = y - 1 from the ring (density, psi), ghost rows at the walls
     const int j = y - 1;
     const bool doG = j >= jb0 && j <= jb1;
     C fg[9], rj = (C)0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fg[i] = (C)0;
     if (doG && actBg) {
       const bool bot = j == 1, top = j == ny - 2;
       const int sm = (j + 2) % 3, sc = j % 3, sp = (j + 1) % 3;  // ring slots of rows j - 1, j, j + 1
@@ -278,6 +289,9 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
       psB[sc][lx] = node_psi<MIX>(d, rj, dm);
       if (bot) rhB[0][lx] = rj;
       if (top) rhB[1][lx] = rj;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fg[i] = __builtin_nondeterministic_value((C)0);  // never collided
     }
     if (doG && j == ny - 3) rBtop2 = rj;
     // bottom ghost row (row 0, ring slot 0) once rows 1 and 2 are in: row 1's densities through LDS
@@ -310,7 +324,12 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
 #pragma unroll
     for (int i = 0; i < 9; ++i) fBp[i] = fg[i];
     rBp = rj;
-    if (y == yend) break;
+    return y == yend;
+  };
+  for (int y = ya0;; y += 3) {
+    if (row(y)) break;
+    if (row(y + 1)) break;
+    if (row(y + 2)) break;
   }
 }
 
