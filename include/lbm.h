@@ -96,12 +96,12 @@ typedef struct {
   int32_t check_every;    /* steps between device checks of mass, non-finite density and clamps; 0 = none */
   int32_t strip_rows;     /* rows per block strip of the step kernels; 0 = library default: for the one-step
                              kernel about two blocks per compute unit over all instances, 2..32 rows (FP32) / 2..64
-                             (FP64); 32 output rows for the two-step kernel */
+                             (FP64); for the two-step kernel one round of resident blocks */
   int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step (any precision) */
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects the one-step kernel with 1, 2, 4 or 8 wavefronts
                              (64, 128, 256 or 512 aligned columns) per block, 5..8 the same with the next row's
-                             loads in flight; 9..12 the two-step kernel (two time steps per launch, tau = 1 BGK
-                             with geometric walls, any precision; other selections step one at a time) with 1, 2,
+                             loads in flight; 9..12 the two-step kernel (two time steps per launch, geometric
+                             walls, any collision and precision; other boundaries step one at a time) with 1, 2,
                              4 or 8 wavefronts per block; 0 = library default (two-step where it applies on
                              contexts of at least 2^22 fluid nodes, one-step below).
                              Instance 0's value applies to the whole context (lbm_autotune may change it). Results

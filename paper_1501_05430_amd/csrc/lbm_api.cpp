@@ -448,7 +448,7 @@ struct lbm_ctx {
   std::vector<InstDesc> hdesc;
   std::vector<int32_t> first;       // [n+1] task ranges per instance
   std::vector<WaveTask> tasks;
-  // two steps per launch where the selection allows it (FP32, tau = 1 BGK, geometric walls)
+  // two steps per launch where the selection allows it (geometric walls)
   bool step2 = false;
   int waves2 = kDefaultWaves2;
   std::vector<int32_t> first2;      // [n+1] ranges of the two-step tasks
@@ -478,9 +478,9 @@ struct lbm_ctx {
   }
 
   bool f32() const { return storage != STORE_F64; }
-  // the two-step kernel covers the selection: tau = 1 BGK and geometric walls everywhere (any storage)
+  // the two-step kernel covers the selection: geometric walls everywhere (any collision, any storage)
   bool step2_ok(int sel) const {
-    if (!step2 || !tau1(sel)) return false;
+    if (!step2) return false;
     for (int i = 0; i < n(); ++i)
       if ((sel < 0 || i == sel) && inst[i].p.boundary != LBM_WALLS_Y) return false;
     return true;
@@ -714,7 +714,7 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     // two-step kernel: one round of resident blocks over all instances, each task a tile of a strip; fewer, taller
     // strips than that leave compute units idle, more add a partial second round and more halo rows
     int per_cu = 0;
-    if (step2_blocks_per_cu(c->waves2, c->storage, &per_cu) == hipSuccess &&
+    if (step2_blocks_per_cu(c->waves2, c->storage, !c->tau1(-1), &per_cu) == hipSuccess &&
         per_cu > 0) {
       const int wmax = 64 * c->waves2 - kStep2Halo;
       double tile_rows = 0;
@@ -882,7 +882,7 @@ int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check, int
     const bool chk = chk_at(i);
     if (two && !chk && i + 1 < count && !chk_at(i + 1)) {
       if (!dry)
-        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage,
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage, !c->tau1(sel),
                              (int)(nl & 1), c->stream));
       i += 2;
       continue;
@@ -1226,7 +1226,7 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
     for (int k = 0; k <= launches; ++k) {
       if (k == 1) HIP_TRY(hipEventRecord(e0, c->stream));  // launch 0 warms up
       if (two)
-        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage, 0,
+        HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage, !c->tau1(inst), 0,
                              c->stream));
       else
         HIP_TRY(launch_step(c->storage, false, c->tau1(inst), c->waves, c->prefetch, c->d_desc(), c->d_tasks() + a,

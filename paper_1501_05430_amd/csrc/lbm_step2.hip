@@ -36,7 +36,7 @@ constexpr int kXcds = 8;
 
 // FP64: at least two blocks per compute unit, which caps the registers at 256 (two wavefronts per SIMD; the ring of
 // FP64 rows allows two blocks of four wavefronts per compute unit)
-template <class S, int W, bool MIX>
+template <class S, int W, bool MIX, bool GEN>
 __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1)) void k_step2(const InstDesc* __restrict__ descs,
                                                     const WaveTask* __restrict__ tasks, int ntasks, int flip) {
   typedef typename ComputeOf<S>::type C;
@@ -150,20 +150,49 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   };
 
   const C inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
+  // GEN: the instance's own collision, a branch uniform over the block: MRT (Eq. 15) with the surface-tension source
+  // (Eq. 16-17) where set, else BGK at any tau; otherwise the tau = 1 BGK specialisation
+  const bool mrt = GEN && d.mrt != 0, kap = mrt && d.kq != 0.0;
+  const C Ac = (C)d.A, s_e = (C)d.s_e, s_eps = (C)d.s_eps, s_q = (C)d.s_q, kq = (C)d.kq;
 
-  // Eq. 9 and the collision of one node (tau = 1 BGK), as in the one-step kernel: FP32, or for MIX the force,
-  // velocity, equilibrium and forcing in FP64
+  // Eq. 9 and the collision of one node, as in the one-step kernel: FP32 or FP64, or for MIX the force, velocity,
+  // equilibrium and forcing in FP64 (and the whole MRT collision)
   auto force_collide = [&](const C (&f)[9], C rho, C pc, C pcL, C pcR, C pm, C pmL, C pmR, C pn, C pnL, C pnR,
                            C (&fs)[9]) {
     if constexpr (MIX) {
       double Fx, Fy;
       hybrid_force<double>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
       const double r = (double)rho;
-      collide<C, double, true>(f, r, r - d.rho0, Fx, Fy, d.inv_tau, d.force_pref, rcp64(r), fs);
+      if constexpr (GEN) {
+        if (mrt) {
+          double fd[9], fsd[9], qxx = 0.0, qyy = 0.0, qxy = 0.0;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
+          if (kap) qtensor<double>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, d.A, d.kq, qxx, qyy, qxy);
+          collide_mrt<double>(fd, r, r - d.rho0, Fx, Fy, rcp64(r), d.s_e, d.s_eps, d.s_q, d.inv_tau, qxx, qyy, qxy,
+                              fsd);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fs[i] = (C)fsd[i];
+        } else {
+          collide<C, double, false>(f, r, r - d.rho0, Fx, Fy, d.inv_tau, d.force_pref, rcp64(r), fs);
+        }
+      } else {
+        collide<C, double, true>(f, r, r - d.rho0, Fx, Fy, d.inv_tau, d.force_pref, rcp64(r), fs);
+      }
     } else {
       C Fx, Fy;
       hybrid_force<C>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
-      collide<C, C, true>(f, rho, rho - rho0, Fx, Fy, inv_tau, pref, (C)1 / rho, fs);
+      if constexpr (GEN) {
+        if (mrt) {
+          C qxx = (C)0, qyy = (C)0, qxy = (C)0;
+          if (kap) qtensor<C>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, Ac, kq, qxx, qyy, qxy);
+          collide_mrt<C>(f, rho, rho - rho0, Fx, Fy, (C)1 / rho, s_e, s_eps, s_q, inv_tau, qxx, qyy, qxy, fs);
+        } else {
+          collide<C, C, false>(f, rho, rho - rho0, Fx, Fy, inv_tau, pref, (C)1 / rho, fs);
+        }
+      } else {
+        collide<C, C, true>(f, rho, rho - rho0, Fx, Fy, inv_tau, pref, (C)1 / rho, fs);
+      }
     }
   };
 
@@ -333,47 +362,60 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   }
 }
 
-template <class S, int W, bool MIX>
+template <class S, int W, bool MIX, bool GEN>
 int occupancy_of(int* blocks) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<S, W, MIX>, WAVE * W, 0);
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<S, W, MIX, GEN>, WAVE * W, 0);
 }
 
-template <class S, bool MIX>
+template <class S, bool MIX, bool GEN>
 hipError_t blocks_per_cu(int waves, int* blocks) {
   switch (waves) {
-    case 1: return (hipError_t)occupancy_of<S, 1, MIX>(blocks);
-    case 2: return (hipError_t)occupancy_of<S, 2, MIX>(blocks);
-    case 4: return (hipError_t)occupancy_of<S, 4, MIX>(blocks);
-    default: return (hipError_t)occupancy_of<S, 8, MIX>(blocks);
+    case 1: return (hipError_t)occupancy_of<S, 1, MIX, GEN>(blocks);
+    case 2: return (hipError_t)occupancy_of<S, 2, MIX, GEN>(blocks);
+    case 4: return (hipError_t)occupancy_of<S, 4, MIX, GEN>(blocks);
+    default: return (hipError_t)occupancy_of<S, 8, MIX, GEN>(blocks);
   }
 }
 
-template <class S, bool MIX>
+template <class S, bool MIX, bool GEN>
 void launch2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip, unsigned grid,
              hipStream_t s) {
   switch (waves) {
-    case 1: hipLaunchKernelGGL((k_step2<S, 1, MIX>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 2: hipLaunchKernelGGL((k_step2<S, 2, MIX>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 4: hipLaunchKernelGGL((k_step2<S, 4, MIX>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    default: hipLaunchKernelGGL((k_step2<S, 8, MIX>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 1: hipLaunchKernelGGL((k_step2<S, 1, MIX, GEN>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 2: hipLaunchKernelGGL((k_step2<S, 2, MIX, GEN>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 4: hipLaunchKernelGGL((k_step2<S, 4, MIX, GEN>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    default: hipLaunchKernelGGL((k_step2<S, 8, MIX, GEN>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
   }
+}
+
+template <bool GEN>
+hipError_t blocks_for(int waves, int storage, int* blocks) {
+  if (storage == STORE_F64) return blocks_per_cu<double, false, GEN>(waves, blocks);
+  return storage == STORE_F32M ? blocks_per_cu<float, true, GEN>(waves, blocks)
+                               : blocks_per_cu<float, false, GEN>(waves, blocks);
+}
+
+template <bool GEN>
+void launch_for(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage, int flip,
+                unsigned grid, hipStream_t s) {
+  if (storage == STORE_F64) launch2<double, false, GEN>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  else if (storage == STORE_F32M) launch2<float, true, GEN>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  else launch2<float, false, GEN>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
 }
 
 }  // namespace
 
-hipError_t step2_blocks_per_cu(int waves, int storage, int* blocks) {
+hipError_t step2_blocks_per_cu(int waves, int storage, bool general, int* blocks) {
   *blocks = 0;
-  if (storage == STORE_F64) return blocks_per_cu<double, false>(waves, blocks);
-  return storage == STORE_F32M ? blocks_per_cu<float, true>(waves, blocks) : blocks_per_cu<float, false>(waves, blocks);
+  return general ? blocks_for<true>(waves, storage, blocks) : blocks_for<false>(waves, storage, blocks);
 }
 
-hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage, int flip,
-                        hipStream_t s) {
+hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage,
+                        bool general, int flip, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(((ntasks + kXcds - 1) / kXcds) * kXcds);
-  if (storage == STORE_F64) launch2<double, false>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
-  else if (storage == STORE_F32M) launch2<float, true>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
-  else launch2<float, false>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+  if (general) launch_for<true>(d_desc, d_tasks, ntasks, waves, storage, flip, grid, s);
+  else launch_for<false>(d_desc, d_tasks, ntasks, waves, storage, flip, grid, s);
   return hipGetLastError();
 }
 

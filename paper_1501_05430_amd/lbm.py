@@ -230,8 +230,7 @@ class LBM:
 
     def _two_step_applies(self, inst):
         sel = self.params if inst < 0 else [self.params[inst]]
-        return all(p.precision != _lib.LBM_F64 and p.tau == 1.0 and p.boundary == 0 and not any(p.mrt_rates)
-                   and p.kappa == 0.0 for p in sel)
+        return all(p.boundary == BOUNDARIES["walls"] for p in sel)
 
     def _tuning_key(self, inst, trial_steps):
         """Device, library build and everything about the instances that decides a launch's time."""

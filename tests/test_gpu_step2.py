@@ -1,8 +1,8 @@
 """The two-step kernel (two time steps per launch, lbm_step2.hip) against one-step launches, bit for bit in every
 precision, and against the FP64 reference, through the C-ABI. It runs the same per-node arithmetic, so every population must
 match exactly: across lattice shapes (ragged tiles, lattices narrower than a tile, the fewest rows), block shapes,
-strip heights, odd and even step counts, both EOS, the force and wetting options, checked steps in between and the
-batched form."""
+strip heights, odd and even step counts, both EOS, the force and wetting options, the general collisions (MRT with
+the surface-tension source, BGK at any tau), checked steps in between and the batched form."""
 import math
 
 import numpy as np
@@ -135,12 +135,80 @@ def test_batched_two_step_equals_single_contexts():
 
 
 def test_selection_outside_the_two_step_form_steps_one_at_a_time():
-    """MRT, Martys-Chen walls and periodic rows are one-step only: a context asking for the two-step kernel runs
-    them with one-step launches (same results as asking for one-step launches)."""
+    """Martys-Chen walls and periodic rows are one-step only: a context asking for the two-step kernel runs them with
+    one-step launches (same results as asking for one-step launches)."""
     case = case_of(120, 40, 0.8, 60.0, 90.0, [(60, 0.5, 12.0)])
-    for kw in (dict(kappa=0.3), dict(boundary="martys_chen", G_w=(-0.2, -0.2)), dict(boundary="periodic")):
+    for kw in (dict(boundary="martys_chen", G_w=(-0.2, -0.2)), dict(boundary="periodic")):
         a, b, _, _ = pair(case, 15, 11, **kw)
         assert np.array_equal(a, b), kw
+
+
+GENERAL = [dict(kappa=0.5), dict(mrt=(1.2, 0.8, 1.1), kappa=-0.4), dict(mrt=(0.9, 1.3, 1.0), tau=0.8),
+           dict(tau=0.8), dict(tau=1.3, A=-0.3, body_force=(1e-6, -2e-6)), dict(kappa=0.5, piecewise=PW100)]
+
+
+@pytest.mark.parametrize("precision", ["f32_shifted", "f32_shifted_mixed", "f64"])
+@pytest.mark.parametrize("kw", GENERAL)
+@pytest.mark.parametrize("variant,rows", [(11, 9), (9, 4)])
+def test_two_step_general_collision_bitwise(precision, kw, variant, rows):
+    """The general instance of the two-step kernel (MRT of Eq. 15 with the source of Eq. 16-17, or BGK at any tau)
+    against one-step launches of the general one-step kernel, bit for bit, over 36 steps."""
+    import paper_1501_05430_amd as P
+    T = 0.5 if "piecewise" in kw else 0.8
+    case = case_of(200, 60, T, 50.0, 125.0, [(100, 0.5, 22.0), (40, 35, 7.0)])
+    extra = dict(kw)
+    pw = extra.pop("piecewise", None)
+    sims = []
+    for v, h in ((5, 0), (variant, rows)):
+        s = P.LBM(P.make_params(case.nx, case.ny, T, precision=precision, step_variant=v, strip_rows=h,
+                                piecewise=pw, **P.fp32_options(T, precision, piecewise=pw), **extra))
+        s.apply_wetting(case.theta_bottom, case.theta_top)
+        s.init_droplet(case.xc, case.yc, case.R)
+        s.step(36)
+        sims.append(s)
+    a, b = sims[0].populations(), sims[1].populations()
+    for s in sims:
+        s.close()
+    assert np.isfinite(a).all()
+    assert np.array_equal(a, b), np.abs(a - b).max()
+
+
+@pytest.mark.parametrize("kw", [dict(kappa=0.5), dict(mrt=(1.2, 0.8, 1.1), tau=0.9)])
+def test_two_step_general_collision_vs_reference(kw):
+    """FP64 through two-step launches of the general kernel against the FP64 reference, element by element
+    (1e-12 of the largest population) after 60 steps."""
+    case = case_of(160, 48, 0.75, 55.0, 100.0, [(80, W.wall_cap_centre(16.0, math.radians(55)), 16.0), (30, 30, 6)])
+    sim = gpu_sim(case, precision="f64", step_variant=11, strip_rows=7, **kw)
+    ref = oracle_sim(case, **kw)
+    sim.step(60)
+    ref.run(60)
+    f_ref = oracle_pops(ref)
+    err = np.abs(sim.populations() - f_ref).max() / np.abs(f_ref).max()
+    sim.close()
+    assert err <= 1e-12, err
+
+
+def test_batched_two_step_mixes_collisions():
+    """One two-step launch over instances with different collisions (MRT with the source, BGK at tau = 0.8 and 0.9)
+    equals each instance stepped alone with one-step launches, bit for bit. (A tau = 1 BGK instance in such a batch
+    takes the general BGK form, whose rounding differs from the tau = 1 specialisation's, so none is included.)"""
+    import paper_1501_05430_amd as P
+    opts = [dict(tau=0.9), dict(kappa=0.5), dict(tau=0.8), dict(mrt=(1.2, 0.8, 1.1), kappa=0.3)]
+    cases = [case_of(nx, ny, 0.8, th, 90.0, [(nx / 2, 0.5, 0.3 * ny)])
+             for nx, ny, th in ((128, 48, 60.0), (97, 33, 120.0), (200, 40, 80.0), (64, 64, 45.0))]
+    params = [P.make_params(c.nx, c.ny, 0.8, precision="f32_shifted", step_variant=11, strip_rows=6,
+                            **P.fp32_options(0.8, "f32_shifted"), **o) for c, o in zip(cases, opts)]
+    batch = P.LBM(params)
+    for i, c in enumerate(cases):
+        batch.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
+        batch.init_droplet(c.xc, c.yc, c.R, inst=i)
+    batch.step(24, inst=-1)
+    for i, (c, o) in enumerate(zip(cases, opts)):
+        single = gpu_sim(c, precision="f32_shifted", step_variant=5, **o)
+        single.step(24)
+        assert np.array_equal(batch.populations(inst=i), single.populations()), (i, o)
+        single.close()
+    batch.close()
 
 
 @pytest.mark.parametrize("steps", [100, 101])
