@@ -39,24 +39,28 @@ TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "traffic_step2_f64_c3.json")
 # this script (FETCH_SIZE, then WRITE_SIZE) by `bench.py --traffic-summary <name>`
 TRAFFIC_SPECS = {
     "step2_f32_c3": dict(
-        match="k_step2<float, 4, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        match="k_step2<float, 4, false, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<W=4> (two time steps per launch; FP32 storage shifted by rho_v, FP32 arithmetic with the FP64 "
              "EOS in the vapour, tau = 1 BGK, geometric walls), 4096x2048 lattice, T = 0.5 T_c, theta = 45 deg, "
              "65 droplets; default shape"),
     "step2_mixed_c3": dict(
-        match="k_step2<float, 4, true>", workload="c3",
+        match="k_step2<float, 4, true, false>", workload="c3",
         args="--precision f32_shifted_mixed --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<W=4> in the mixed form (FP32 storage shifted by rho_v and FP32 sums; psi, force, equilibrium "
              "and forcing in FP64), same lattice and shape"),
     "step2_f64_c3": dict(
-        match="k_step2<double, 4, false>", workload="c3", bytes_per_update=144,
+        match="k_step2<double, 4, false, false>", workload="c3", bytes_per_update=144,
         args="--precision f64 --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<double, W=4> (two time steps per launch in FP64: storage and arithmetic), same lattice; "
              "strips of at most 24 output rows"),
     "step2_f32_batched_c4": dict(
-        match="k_step2<float, ", exclude=", true>", workload="c4", args="--batched-only --steps 40",
+        match="k_step2<float, ", exclude=", true", workload="c4", args="--batched-only --steps 40",
         desc="k_step2 (two time steps per launch, the autotuner's block shape) over the 256-instance batch (sizes "
              "64x32 .. 512x256, T/T_c in [0.6, 0.9], theta in [20, 160] deg, seed 1501), FP32 shifted by rho_v"),
+    "step2_general_paper_setting_c3": dict(
+        match="k_step2<float, 4, false, true>", workload="c3", args="--paper-setting-only --steps 20",
+        desc="k_step2<float, W=4, general collision> in the paper's setting (piecewise-linear EOS at a density ratio "
+             "of 1000, kappa = 0.5, MRT with diag(0,1,...,1)), same lattice, FP32 shifted by rho_v"),
 }
 COPY_KERNEL = "k_copy<HIP_vector_type<float, 4u> >"
 
@@ -391,8 +395,8 @@ def adjoint_rate(case, calls=30, dtype="f64", **kw):
 def piecewise_rate(case, steps=2000, kappa=0.0):
     """The same lattice and droplets with the piecewise-linear EOS of Eq. 11 at a density ratio of 1000 (Table 1:
     theta = 0.2, -0.01, 0.33333 with rho_v = 1), FP32 shifted by rho_v as the headline run. kappa != 0 adds the
-    surface-tension source of Eq. 16-17 with the relaxation matrix diag(0,1,...,1) of Sec. 3.1 (the MRT collision
-    in the general step kernel): the paper's own setting."""
+    surface-tension source of Eq. 16-17 with the relaxation matrix diag(0,1,...,1) of Sec. 3.1 (the MRT collision,
+    in the general instance of the two-step kernel): the paper's own setting."""
     pw = (0.2, -0.01, 0.33333, 1.0, 1000.0)
     sim = make_sim(case, "f32_shifted", check_every=100, piecewise=pw, kappa=kappa)
     sim.step(50)
@@ -402,9 +406,10 @@ def piecewise_rate(case, steps=2000, kappa=0.0):
     m1 = sim.mass()
     sim.close()
     nodes = case.fluid_nodes
-    return {"mlups": round(nodes * steps / ms / 1e3, 1), "gbs_alg": round(72 * nodes * steps / ms / 1e6, 1),
-            "steps": steps, "stable": stable and d["nonfinite"] == 0, "psi_clamps": d["psi_clamps"],
-            "mass_drift": abs(m1 - m0) / m0}
+    ach = 72 * nodes * steps / ms / 1e6
+    return {"mlups": round(nodes * steps / ms / 1e3, 1), "gbs_alg": round(ach, 1),
+            "frac_of_hbm_peak": round(ach / PEAK_HBM_GBS, 4), "steps": steps,
+            "stable": stable and d["nonfinite"] == 0, "psi_clamps": d["psi_clamps"], "mass_drift": abs(m1 - m0) / m0}
 
 
 def mixed_rate(case, steps=1000):
@@ -433,6 +438,8 @@ def main():
                     help="autotune the step kernel's block shape first (default: the library's defaults)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 256-instance batched leg and print its JSON (for profiling that launch)")
+    ap.add_argument("--paper-setting-only", action="store_true",
+                    help="only the paper's setting on the headline lattice (piecewise EOS, kappa = 0.5, MRT), --steps")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint legs on the headline lattice and print their JSON (for profiling)")
     ap.add_argument("--precision", default="f32_shifted", choices=["f32_shifted", "f32_shifted_mixed", "f64"],
@@ -457,6 +464,10 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched_256": batched_vs_plain(steps_batched=args.steps, steps_plain=0)}), flush=True)
+        return
+    if args.paper_setting_only:
+        print(json.dumps({"paper_setting_ratio1000_kappa05_same_lattice":
+                          piecewise_rate(W.c3_large(), steps=args.steps, kappa=0.5)}), flush=True)
         return
     if args.adjoint_only:
         case = W.c3_large()
@@ -514,8 +525,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
             # current), traffic_gbs those bytes over this run's time per launch
-            "kernel": f"k_step2<{'double' if f64 else 'float'}, 4, {'true' if mixed else 'false'}> (two time steps "
-                      "per launch)", "steps_per_launch": 2,
+            "kernel": f"k_step2<{'double' if f64 else 'float'}, 4, {'true' if mixed else 'false'}, false> (two time "
+                      "steps per launch)", "steps_per_launch": 2,
             "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic
