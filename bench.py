@@ -380,8 +380,9 @@ def adjoint_rate(case, calls=30, dtype="f64", **kw):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(sim.stream)
-    for _ in range(calls):
-        sim.adjoint_step(f, lam1, lam0, theta_bar, G_bar)
+    with torch.cuda.stream(sim.stream):  # queued back to back on the library's stream, as a reverse rollout runs them
+        for _ in range(calls):
+            sim.adjoint_step(f, lam1, lam0, theta_bar, G_bar)
     e1.record(sim.stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / calls

@@ -110,7 +110,7 @@ class LBM:
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._take_over()
         ctx = C.c_void_p()
         check(self.lib.lbm_create(arr, self.n, C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
                                   C.byref(ctx)))
@@ -292,7 +292,7 @@ class LBM:
         if isinstance(f, torch.Tensor):
             assert f.shape == (9, p.ny - 2, p.nx) and f.dtype == torch.float64 and f.is_cuda
             f = f.contiguous()
-            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            self._take_over()
             check(self.lib.lbm_set_populations(self.ctx, inst, C.c_void_p(f.data_ptr()), 1))
             f.record_stream(self.stream)
         else:
@@ -315,7 +315,7 @@ class LBM:
         import torch
         assert state.is_cuda and state.is_contiguous() and state.dtype == torch.uint8
         assert state.numel() == self.state_bytes(inst)
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._take_over()
         check(self.lib.lbm_set_state(self.ctx, inst, C.c_void_p(state.data_ptr())))
         state.record_stream(self.stream)
 
@@ -337,7 +337,7 @@ class LBM:
             assert t.is_cuda and t.is_contiguous() and t.dtype == dt and t.numel() == 9 * (p.ny - 2) * p.nx
         for t, size in ((theta_bar, 2 * p.nx), (G_bar, 2)):
             assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.numel() == size
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._take_over()
         fn = self.lib.lbm_adjoint_step if dt == torch.float64 else self.lib.lbm_adjoint_step_f32
         check(fn(self.ctx, inst, C.c_void_p(f_n.data_ptr()), C.c_void_p(lam_np1.data_ptr()),
                  C.c_void_p(lam_n.data_ptr()), C.c_void_p(theta_bar.data_ptr()), C.c_void_p(G_bar.data_ptr())))
@@ -354,16 +354,27 @@ class LBM:
         assert lam.numel() == 9 * (p.ny - 2) * p.nx
         for t, size in ((theta_bar, 2 * p.nx), (G_bar, 2)):
             assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.numel() == size
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._take_over()
         fn = self.lib.lbm_adjoint_seed_rho if lam.dtype == torch.float64 else self.lib.lbm_adjoint_seed_rho_f32
         check(fn(self.ctx, inst, C.c_void_p(grad_rho.data_ptr()), C.c_void_p(lam.data_ptr()),
                  C.c_void_p(theta_bar.data_ptr()), C.c_void_p(G_bar.data_ptr())))
         self._hand_over()
 
+    def _take_over(self):
+        """Make the library's stream wait for the work queued on torch's current stream (device inputs). Nothing to
+        do when that stream is the library's own (inside `with torch.cuda.stream(sim.stream)`): a wait across two
+        streams costs a round trip between two hardware queues on every call."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
     def _hand_over(self):
         """Make torch's current stream wait for the work queued on the library's stream (device outputs)."""
         import torch
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
 
 
 def deg(rad):
