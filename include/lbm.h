@@ -242,8 +242,8 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
 /* The step shape of a context: what lbm_autotune chose (or the defaults), to keep and re-apply later without the
  * trials (the Python binding keeps a JSON cache of these records, keyed by the device and the instances). */
 typedef struct {
-  int32_t two_step;  /* 1: two time steps per launch wherever the selection allows it (FP32 storage, tau = 1 BGK,
-                        geometric walls); 0: one step per launch */
+  int32_t two_step;  /* 1: two time steps per launch wherever the selection allows it (geometric walls: any
+                        collision and precision); 0: one step per launch */
   int32_t waves;     /* one-step kernel: wavefronts per block, 1, 2, 4 or 8 */
   int32_t prefetch;  /* one-step kernel: 1 = the next row's loads in flight, 0 = not */
   int32_t waves2;    /* two-step kernel: wavefronts per block, 1, 2, 4 or 8 */
