@@ -413,6 +413,25 @@ def piecewise_rate(case, steps=2000, kappa=0.0):
             "stable": stable and d["nonfinite"] == 0, "psi_clamps": d["psi_clamps"], "mass_drift": abs(m1 - m0) / m0}
 
 
+def martys_chen_rate(case, steps=1000):
+    """The comparison method of Sec. 3 on the same lattice and droplets: Martys-Chen walls (the fluid-solid force of
+    Eq. 14, G_w = -1.6 on both walls, about 94 deg in Sec. 3.1's setting) with the piecewise-linear EOS of Table 1
+    at a density ratio of 10 and kappa = 0.5, FP32 shifted by rho_v, through the general instance of the two-step
+    kernel."""
+    pw = (0.25, -0.02, 0.3, 1.0, 10.0)
+    sim = make_sim(case, "f32_shifted", check_every=100, piecewise=pw, kappa=0.5, boundary="martys_chen",
+                   G_w=(-1.6, -1.6))
+    sim.step(50)
+    ms, stable = timed_steps(sim, steps)
+    d = sim.diag()
+    sim.close()
+    nodes = case.fluid_nodes
+    ach = 72 * nodes * steps / ms / 1e6
+    return {"mlups": round(nodes * steps / ms / 1e3, 1), "gbs_alg": round(ach, 1),
+            "frac_of_hbm_peak": round(ach / PEAK_HBM_GBS, 4), "steps": steps,
+            "stable": stable and d["nonfinite"] == 0}
+
+
 def mixed_rate(case, steps=1000):
     """The FP32 storage form with the force and equilibrium in FP64 (LBM_F32_SHIFTED_MIXED) on the same lattice,
     in the same launch configuration: the same 72 B per fluid node and step."""
@@ -552,6 +571,7 @@ def main():
             "adjoint_fp32_storage_same_lattice": adjoint_rate(case, dtype="f32"),
             "piecewise_eos_ratio1000_same_lattice": piecewise_rate(case),
             "paper_setting_ratio1000_kappa05_same_lattice": piecewise_rate(case, kappa=0.5),
+            "martys_chen_ratio10_kappa05_same_lattice": martys_chen_rate(case),
             # the reverse step in the paper's setting (MRT form with the surface-tension source)
             "adjoint_paper_setting_same_lattice": adjoint_rate(case, piecewise=(0.2, -0.01, 0.33333, 1.0, 1000.0),
                                                                kappa=0.5),

@@ -100,9 +100,9 @@ typedef struct {
   int32_t enable_adjoint; /* 1: reserve workspace for lbm_adjoint_step (any precision) */
   int32_t step_variant;   /* step kernel shape: k = 1..4 selects the one-step kernel with 1, 2, 4 or 8 wavefronts
                              (64, 128, 256 or 512 aligned columns) per block, 5..8 the same with the next row's
-                             loads in flight; 9..12 the two-step kernel (two time steps per launch, geometric
-                             walls, any collision and precision; other boundaries step one at a time) with 1, 2,
-                             4 or 8 wavefronts per block; 0 = library default (two-step where it applies on
+                             loads in flight; 9..12 the two-step kernel (two time steps per launch, geometric or
+                             Martys-Chen walls, any collision and precision; periodic rows step one at a time) with
+                             1, 2, 4 or 8 wavefronts per block; 0 = library default (two-step where it applies on
                              contexts of at least 750 000 fluid nodes, one-step below).
                              Instance 0's value applies to the whole context (lbm_autotune may change it). Results
                              do not depend on it (bitwise). */
@@ -242,8 +242,8 @@ int lbm_autotune(lbm_ctx* c, int32_t inst, int32_t trial_steps, int32_t* chosen)
 /* The step shape of a context: what lbm_autotune chose (or the defaults), to keep and re-apply later without the
  * trials (the Python binding keeps a JSON cache of these records, keyed by the device and the instances). */
 typedef struct {
-  int32_t two_step;  /* 1: two time steps per launch wherever the selection allows it (geometric walls: any
-                        collision and precision); 0: one step per launch */
+  int32_t two_step;  /* 1: two time steps per launch wherever the selection allows it (walls, not periodic rows:
+                        any collision and precision); 0: one step per launch */
   int32_t waves;     /* one-step kernel: wavefronts per block, 1, 2, 4 or 8 */
   int32_t prefetch;  /* one-step kernel: 1 = the next row's loads in flight, 0 = not */
   int32_t waves2;    /* two-step kernel: wavefronts per block, 1, 2, 4 or 8 */

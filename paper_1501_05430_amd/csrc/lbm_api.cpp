@@ -448,7 +448,7 @@ struct lbm_ctx {
   std::vector<InstDesc> hdesc;
   std::vector<int32_t> first;       // [n+1] task ranges per instance
   std::vector<WaveTask> tasks;
-  // two steps per launch where the selection allows it (geometric walls)
+  // two steps per launch where the selection allows it (walls, not periodic rows)
   bool step2 = false;
   int waves2 = kDefaultWaves2;
   std::vector<int32_t> first2;      // [n+1] ranges of the two-step tasks
@@ -470,19 +470,24 @@ struct lbm_ctx {
   double* d_rho_scratch() { return (double*)(ws + L.rho_scratch); }
   int n() const { return (int)inst.size(); }
 
-  // the tau = 1 BGK collision applies when every selected instance has tau == 1 exactly and no MRT rates
+  // the tau = 1 BGK specialisation applies when every selected instance has tau == 1 exactly, no MRT rates and no
+  // Martys-Chen walls (those run the general instances of both step kernels, so that one- and two-step launches
+  // round alike)
   bool tau1(int sel) const {
     for (int i = 0; i < n(); ++i)
-      if ((sel < 0 || i == sel) && (inst[i].p.tau != 1.0 || uses_mrt(inst[i].p))) return false;
+      if ((sel < 0 || i == sel) &&
+          (inst[i].p.tau != 1.0 || uses_mrt(inst[i].p) || inst[i].p.boundary == LBM_WALLS_MARTYS_CHEN))
+        return false;
     return true;
   }
 
   bool f32() const { return storage != STORE_F64; }
-  // the two-step kernel covers the selection: geometric walls everywhere (any collision, any storage)
+  // the two-step kernel covers the selection: walls everywhere, geometric or Martys-Chen (any collision, any
+  // storage); periodic rows step one at a time
   bool step2_ok(int sel) const {
     if (!step2) return false;
     for (int i = 0; i < n(); ++i)
-      if ((sel < 0 || i == sel) && inst[i].p.boundary != LBM_WALLS_Y) return false;
+      if ((sel < 0 || i == sel) && inst[i].p.boundary == LBM_PERIODIC_Y) return false;
     return true;
   }
 

@@ -1,7 +1,8 @@
 // Two time steps per launch (temporal blocking) for the step with tau = 1 BGK-Guo collision and the geometric walls
-// of Sec. 4 (the headline form of the method), in every storage precision. Per lattice update it moves about half
-// the HBM bytes of the one-step kernel (lbm_kernels.hip), whose per-node arithmetic it repeats exactly: the results
-// are bit for bit those of two one-step launches.
+// of Sec. 4 (the headline form of the method), in every storage precision; a general instance covers the other
+// collisions (MRT with the surface-tension source, BGK at any tau) and the Martys-Chen walls of Eq. 14. Per lattice
+// update it moves about half the HBM bytes of the one-step kernel (lbm_kernels.hip), whose per-node arithmetic it
+// repeats exactly: the results are bit for bit those of two one-step launches.
 //
 // A block of W wavefronts owns a tile: output columns [x0, x0 + bw) (bw <= 64 W - 6) of output rows [y0, ylast].
 // Lane l works on column x0 - 3 + l (periodic), so the tile carries three halo columns on each side.
@@ -62,6 +63,9 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   const int x0 = uni(t.x0), y0 = uni(t.y0), bw = uni(t.wh & 0xffff), nrows = uni(t.wh >> 16);
   const int ylast = y0 + nrows - 1;
   const C rho0 = (C)d.rho0;
+  // GEN: Martys-Chen walls (Eq. 14), a branch uniform over the block: solid wall rows (psi = 0 in the ghost rows, no
+  // wetting) and the fluid-solid force on the boundary rows
+  const bool mcw = GEN && d.wall_mc != 0;
   auto wrapc = [&](int x) { x %= nx; return x < 0 ? x + nx : x; };
 
   const int bwA = bw + 6;           // step A's columns: x0 - 3 .. x0 + bw + 2
@@ -123,6 +127,10 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   };
   // ghost row beside wall `wall` from the boundary row yb (r1, halo hr1) and the second row (r2, hr2), Sec. 4
   auto ghostA = [&](int wall, int yb, C r1, C r2, C hr1, C hr2, C& g_rho, C& g_psi, C& gh_psi) {
+    if (mcw) {
+      g_rho = g_psi = gh_psi = (C)0;
+      return;
+    }
     C Lf, Rf;
     xchg(r1, hr1, Lf, Rf);
     C ro = (C)0;
@@ -151,19 +159,24 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
 
   const C inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
   // GEN: the instance's own collision, a branch uniform over the block: MRT (Eq. 15) with the surface-tension source
-  // (Eq. 16-17) where set, else BGK at any tau; otherwise the tau = 1 BGK specialisation
+  // (Eq. 16-17) where set, else BGK at any tau; otherwise the tau = 1 BGK specialisation (geometric walls only)
   const bool mrt = GEN && d.mrt != 0, kap = mrt && d.kq != 0.0;
   const C Ac = (C)d.A, s_e = (C)d.s_e, s_eps = (C)d.s_eps, s_q = (C)d.s_q, kq = (C)d.kq;
+  const C gwb = (C)d.gw_half[0], gwt = (C)d.gw_half[1];  // G_w / 2 of the bottom and top wall
 
-  // Eq. 9 and the collision of one node, as in the one-step kernel: FP32 or FP64, or for MIX the force, velocity,
-  // equilibrium and forcing in FP64 (and the whole MRT collision)
-  auto force_collide = [&](const C (&f)[9], C rho, C pc, C pcL, C pcR, C pm, C pmL, C pmR, C pn, C pnL, C pnR,
-                           C (&fs)[9]) {
+  // Eq. 9 (with Eq. 14 next to solid walls) and the collision of node row y, as in the one-step kernel: FP32 or
+  // FP64, or for MIX the force, velocity, equilibrium and forcing in FP64 (and the whole MRT collision)
+  auto force_collide = [&](int y, const C (&f)[9], C rho, C pc, C pcL, C pcR, C pm, C pmL, C pmR, C pn, C pnL,
+                           C pnR, C (&fs)[9]) {
     if constexpr (MIX) {
       double Fx, Fy;
       hybrid_force<double>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
       const double r = (double)rho;
       if constexpr (GEN) {
+        if (mcw) {
+          if (y == 1) Fy = Fy + d.gw_half[0] * (double)pc;
+          if (y == ny - 2) Fy = Fy - d.gw_half[1] * (double)pc;
+        }
         if (mrt) {
           double fd[9], fsd[9], qxx = 0.0, qyy = 0.0, qxy = 0.0;
 #pragma unroll
@@ -183,6 +196,10 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
       C Fx, Fy;
       hybrid_force<C>(d, pc, pcL, pcR, pm, pmL, pmR, pn, pnL, pnR, Fx, Fy);
       if constexpr (GEN) {
+        if (mcw) {
+          if (y == 1) Fy = Fy + gwb * pc;
+          if (y == ny - 2) Fy = Fy - gwt * pc;
+        }
         if (mrt) {
           C qxx = (C)0, qyy = (C)0, qxy = (C)0;
           if (kap) qtensor<C>(pc, pcL, pcR, pn, pnL, pnR, pm, pmL, pmR, Ac, kq, qxx, qyy, qxy);
@@ -264,7 +281,7 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
     // ---- step A: collide row y into the ring, then bring row y + 2 into the window
     if (y <= ya1 && act) {
       C fs[9];
-      force_collide(fc, rc, pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, fs);
+      force_collide(y, fc, rc, pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, fs);
       const int s = y % 3;
 #pragma unroll
       for (int i = 0; i < 9; ++i) gA[s][i][lx] = fs[i];
@@ -325,17 +342,25 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
     if (doG && j == ny - 3) rBtop2 = rj;
     // bottom ghost row (row 0, ring slot 0) once rows 1 and 2 are in: row 1's densities through LDS
     if (wallB_bot && doG && j == 2 && actBw) {
-      bool gc, dm;
-      const double r0 = ghost_density((double)rhB[0][lx - 1], (double)rhB[0][lx + 1], (double)rhB[0][lx],
-                                      (double)rj, cos_th[col], cot_th[col], iters, d.rho_cap_hi, gc);
-      psB[0][lx] = (C)psi_eval(d, r0, dm);
+      if (mcw) {
+        psB[0][lx] = (C)0;
+      } else {
+        bool gc, dm;
+        const double r0 = ghost_density((double)rhB[0][lx - 1], (double)rhB[0][lx + 1], (double)rhB[0][lx],
+                                        (double)rj, cos_th[col], cot_th[col], iters, d.rho_cap_hi, gc);
+        psB[0][lx] = (C)psi_eval(d, r0, dm);
+      }
     }
     // top ghost row (row ny - 1) after the last gather: row ny - 2's densities through LDS, row ny - 3's own
     if (wallB_top && y == ny && actBw) {
-      bool gc, dm;
-      const double r0 = ghost_density((double)rhB[1][lx - 1], (double)rhB[1][lx + 1], (double)rhB[1][lx],
-                                      (double)rBtop2, cos_th[nx + col], cot_th[nx + col], iters, d.rho_cap_hi, gc);
-      psB[(ny - 1) % 3][lx] = (C)psi_eval(d, r0, dm);
+      if (mcw) {
+        psB[(ny - 1) % 3][lx] = (C)0;
+      } else {
+        bool gc, dm;
+        const double r0 = ghost_density((double)rhB[1][lx - 1], (double)rhB[1][lx + 1], (double)rhB[1][lx],
+                                        (double)rBtop2, cos_th[nx + col], cot_th[nx + col], iters, d.rho_cap_hi, gc);
+        psB[(ny - 1) % 3][lx] = (C)psi_eval(d, r0, dm);
+      }
     }
     __syncthreads();  // step B's psi of row j (and a ghost row) are in the ring
 
@@ -344,7 +369,7 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
     if (m >= y0 && m <= ylast && actBc) {
       C fs[9];
       const int s0 = (m + 2) % 3, s1 = m % 3, s2 = (m + 1) % 3;  // rows m - 1, m, m + 1
-      force_collide(fBp, rBp, psB[s1][lx], psB[s1][lx - 1], psB[s1][lx + 1], psB[s0][lx], psB[s0][lx - 1],
+      force_collide(m, fBp, rBp, psB[s1][lx], psB[s1][lx - 1], psB[s1][lx + 1], psB[s0][lx], psB[s0][lx - 1],
                     psB[s0][lx + 1], psB[s2][lx], psB[s2][lx - 1], psB[s2][lx + 1], fs);
       const unsigned off = (unsigned)((m - 1) * pitch + col);
 #pragma unroll

@@ -230,7 +230,7 @@ class LBM:
 
     def _two_step_applies(self, inst):
         sel = self.params if inst < 0 else [self.params[inst]]
-        return all(p.boundary == BOUNDARIES["walls"] for p in sel)
+        return all(p.boundary != BOUNDARIES["periodic"] for p in sel)
 
     def _tuning_key(self, inst, trial_steps):
         """Device, library build and everything about the instances that decides a launch's time."""
