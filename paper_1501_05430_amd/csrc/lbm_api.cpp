@@ -237,7 +237,7 @@ constexpr int kMaxStripRows2F64 = 24;
 // against 27.7 in FP32), above it two steps per launch win (1448 x 724: 46.8 against 32.2, FP64 40.7 against 25.8;
 // 2048 x 1024: 68.8 against 61.5; 4096 x 2048: 92.4 against 65, FP64 50.3 against 34.9).
 constexpr double kStep2MinNodes = 750000.0;
-constexpr int kStep2Halo = 6;  // step A columns beyond a two-step tile's outputs (three per side)
+constexpr int kStep2Halo = 8;  // lanes beyond a two-step tile's outputs (three of step A and one of psi per side)
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
 static_assert(sizeof(lbm_params) == 10 * 4 + 22 * 8, "lbm_params layout: 10 int32 then 22 double, no padding");

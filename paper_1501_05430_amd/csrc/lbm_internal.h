@@ -69,8 +69,8 @@ hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefe
                        int down = -1);
 // Two steps per launch (lbm_step2.hip): geometric walls (every instance of the launch); general = false for the
 // tau = 1 BGK collision everywhere, true for each instance's own (MRT with the surface-tension source, or BGK at
-// any tau). Tasks are tiles: output columns [x0, x0 + width) with width <= 64 waves - 6 (the kernel adds three halo
-// columns per side), output rows [y0, y0 + nrows). Reads buffer cur ^ flip, writes the other one (as one one-step
+// any tau). Tasks are tiles: output columns [x0, x0 + width) with width <= 64 waves - 8 (the kernel adds four halo
+// lanes per side), output rows [y0, y0 + nrows). Reads buffer cur ^ flip, writes the other one (as one one-step
 // launch). storage: STORE_F64, STORE_F32 or STORE_F32M (the mixed arithmetic of LBM_F32_SHIFTED_MIXED).
 hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage,
                         bool general, int flip, hipStream_t s);

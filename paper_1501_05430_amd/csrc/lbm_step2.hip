@@ -4,22 +4,26 @@
 // update it moves about half the HBM bytes of the one-step kernel (lbm_kernels.hip), whose per-node arithmetic it
 // repeats exactly: the results are bit for bit those of two one-step launches.
 //
-// A block of W wavefronts owns a tile: output columns [x0, x0 + bw) (bw <= 64 W - 6) of output rows [y0, ylast].
-// Lane l works on column x0 - 3 + l (periodic), so the tile carries three halo columns on each side.
-//  * Step A (t -> t+1) is the one-step kernel's row walk over all 64 W lanes: the populations g^t are gathered from
+// A block of W wavefronts owns a tile: output columns [x0, x0 + bw) (bw <= 64 W - 8) of output rows [y0, ylast].
+// Lane l works on column x0 - 4 + l (periodic): step A collides three halo columns on each side of the outputs, and
+// the outermost lane on each side only supplies psi, so every wavefront runs the same instructions (a halo column
+// gathered by an edge lane on top of its own would load the two edge wavefronts, and through the barriers every
+// wavefront, with one more gather and psi per row).
+//  * Step A (t -> t+1) is the one-step kernel's row walk over the tile's lanes: the populations g^t are gathered from
 //    HBM (pull scheme with halfway bounce-back), psi (Eq. 10) is exchanged with the neighbouring lanes, and the
 //    force (Eq. 9) and the collision (Eq. 1-6 at tau = 1) produce g^{t+1} of one row per iteration. The ghost rows
 //    (Eq. 19 / 21) are computed where the walk meets a wall, as in the one-step kernel. g^{t+1} does not go to HBM:
 //    it goes into a three-row ring in LDS.
-//  * Step B (t+1 -> t+2) trails two rows behind: it gathers f^{t+1} of row y-1 from the ring (lanes 1 .. 64 W - 2),
+//  * Step B (t+1 -> t+2) trails two rows behind: it gathers f^{t+1} of row y-1 from the ring (lanes 2 .. bw + 5),
 //    forms rho and psi (psi into a three-row LDS ring of its own), computes its own ghost rows from those densities
 //    at a wall, and collides row y-2 on the output lanes, storing g^{t+2} to HBM.
 // Reach: one step reads populations one column away and psi one more, and a ghost row reads densities one column
-// further, so step B's outputs need step A on three more columns per side; step A's own halo (two columns) is
-// gathered by its edge lanes as in the one-step kernel. In y a strip reads g^t rows y0 - 4 .. ylast + 4.
+// further, so step B's outputs need step A on three more columns per side, and step A psi one column beyond those
+// (the psi-only lanes; at a wall their ghost rows read one column further still). In y a strip reads g^t rows
+// y0 - 4 .. ylast + 4.
 // Per launch and output node: 36 B read (plus the halo share) and 36 B written for two updates.
-// Latency: the rows of g^t (and the edge lanes' halo column) are loaded one row ahead of their use; the row loop is
-// unrolled by the three-row period of the window, so sliding it renames registers instead of copying them.
+// Latency: the rows of g^t are loaded one row ahead of their use; the row loop is unrolled by the three-row period
+// of the window, so sliding it renames registers instead of copying them.
 // Block order: consecutive tasks (tiles of one row band, then the next band) are given to the same XCD, so tiles
 // that share halo rows and boundary cache lines meet in one L2.
 #include <hip/hip_runtime.h>
@@ -68,17 +72,17 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   const bool mcw = GEN && d.wall_mc != 0;
   auto wrapc = [&](int x) { x %= nx; return x < 0 ? x + nx : x; };
 
-  const int bwA = bw + 6;           // step A's columns: x0 - 3 .. x0 + bw + 2
-  const int lx = wv * WAVE + lane;  // position in the tile = column - (x0 - 3)
-  const bool act = lx < bwA;
-  const int col = wrapc(x0 - 3 + (act ? lx : 0));
-  const bool ledge = lx == 0, redge = lx == bwA - 1;
+  const int bwA = bw + 6;           // step A collides columns x0 - 3 .. x0 + bw + 2, on lanes 1 .. bwA
+  const int lx = wv * WAVE + lane;  // position in the tile = column - (x0 - 4)
+  const bool act = lx <= bwA + 1;   // gathers and psi on lanes 0 .. bwA + 1 (the outer two only supply psi)
+  const bool actA = act && lx >= 1 && lx <= bwA;          // step A collides here
+  const int col = wrapc(x0 - 4 + (act ? lx : 0));
+  const bool ledge = lx == 0, redge = lx == bwA + 1;
   const bool edge = ledge || redge;
-  const int hcol = wrapc(ledge ? x0 - 4 : x0 + bw + 3);  // step A's halo column, gathered by an edge lane
-  const int ocol = wrapc(ledge ? x0 - 5 : x0 + bw + 4);  // one further out (ghost tangential difference)
-  const bool actBg = act && lx >= 1 && lx <= bwA - 2;     // step B gathers here
-  const bool actBw = act && lx >= 2 && lx <= bwA - 3;     // step B ghost rows here
-  const bool actBc = lx >= 3 && lx < bw + 3;              // step B output lanes
+  const int ocol = wrapc(ledge ? x0 - 5 : x0 + bw + 4);  // one further out (a ghost row's tangential difference)
+  const bool actBg = lx >= 2 && lx <= bwA - 1;            // step B gathers here
+  const bool actBw = lx >= 3 && lx <= bwA - 2;            // step B ghost rows here
+  const bool actBc = lx >= 4 && lx < bw + 4;              // step B output lanes
 
   // LDS: step A's post-collision rows (ring of 3 rows), row exchange buffers, step B's psi rows (ring of 3 rows,
   // ghost rows included) and step B's boundary-row densities (bottom, top) for its ghost rows.
@@ -87,26 +91,24 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   __shared__ C psB[3][L];
   __shared__ C rhB[2][L];
 
-  // (left, right) neighbours of a per-lane value through xa: put, barrier, get. Edge lanes hold the halo value h.
+  // (left, right) neighbours of a per-lane value through xa: put, barrier, get (lanes 1 .. bwA read them)
   int par = 0;
-  auto xput = [&](C v, C h) {
+  auto xput = [&](C v) {
     if (act) xa[par][lx + 1] = v;
-    if (ledge) xa[par][0] = h;
-    if (redge) xa[par][bwA + 1] = h;
   };
   auto xget = [&](C& l, C& r) {
     l = xa[par][lx];
     r = xa[par][lx + 2];
     par ^= 1;
   };
-  auto xchg = [&](C v, C h, C& l, C& r) {
-    xput(v, h);
+  auto xchg = [&](C v, C& l, C& r) {
+    xput(v);
     __syncthreads();
     xget(l, r);
   };
 
   // ---------------------------------------------------------------------------------------------- step A
-  auto produce = [&](int y, C (&f)[9], C& rho, C& psi, C& hrho, C& hpsi, bool& cl) {
+  auto produce = [&](int y, C (&f)[9], C& rho, C& psi, bool& cl) {
     if (act) {
       gather<S, C>(gin, plane, pitch, nx, ny, col, y, f);
     } else {
@@ -115,24 +117,16 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
     }
     rho = rho0 + sum9(f);
     psi = node_psi<MIX>(d, rho, cl);
-    hrho = (C)0;
-    hpsi = (C)0;
-    if (edge) {
-      C g[9];
-      gather<S, C>(gin, plane, pitch, nx, ny, hcol, y, g);
-      hrho = rho0 + sum9(g);
-      bool dm;
-      hpsi = node_psi<MIX>(d, hrho, dm);
-    }
   };
-  // ghost row beside wall `wall` from the boundary row yb (r1, halo hr1) and the second row (r2, hr2), Sec. 4
-  auto ghostA = [&](int wall, int yb, C r1, C r2, C hr1, C hr2, C& g_rho, C& g_psi, C& gh_psi) {
+  // ghost row beside wall `wall` from the boundary row yb (r1) and the second row (r2), Sec. 4; the outermost lanes'
+  // tangential difference reads one column further out (ocol)
+  auto ghostA = [&](int wall, int yb, C r1, C r2, C& g_rho, C& g_psi) {
     if (mcw) {
-      g_rho = g_psi = gh_psi = (C)0;
+      g_rho = g_psi = (C)0;
       return;
     }
     C Lf, Rf;
-    xchg(r1, hr1, Lf, Rf);
+    xchg(r1, Lf, Rf);
     C ro = (C)0;
     if (edge) {
       C g[9];
@@ -140,21 +134,14 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
       ro = rho0 + sum9(g);
     }
     const int base = wall * nx;
-    double r0 = 0.0, rh0 = 0.0;
-    bool gc = false, gch = false;
+    double r0 = 0.0;
+    bool gc = false;
     if (act)
-      r0 = ghost_density((double)Lf, (double)Rf, (double)r1, (double)r2, cos_th[base + col], cot_th[base + col],
-                         iters, d.rho_cap_hi, gc);
-    if (edge) {
-      const double hl = ledge ? (double)ro : (double)r1;
-      const double hr = ledge ? (double)r1 : (double)ro;
-      rh0 = ghost_density(hl, hr, (double)hr1, (double)hr2, cos_th[base + hcol], cot_th[base + hcol], iters,
-                          d.rho_cap_hi, gch);
-    }
+      r0 = ghost_density(ledge ? (double)ro : (double)Lf, redge ? (double)ro : (double)Rf, (double)r1, (double)r2,
+                         cos_th[base + col], cot_th[base + col], iters, d.rho_cap_hi, gc);
     bool dm;
     g_rho = (C)r0;
     g_psi = (C)psi_eval(d, r0, dm);
-    gh_psi = (C)psi_eval(d, rh0, dm);
   };
 
   const C inv_tau = (C)d.inv_tau, pref = (C)d.force_pref;
@@ -217,37 +204,36 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   const int ya0 = y0 - 2 >= 1 ? y0 - 2 : 1, ya1 = ylast + 2 <= ny - 2 ? ylast + 2 : ny - 2;
   const bool wall_start = ya0 == 1, wall_end = ya1 == ny - 2;
 
-  C tg = (C)0, thg = (C)0;  // step A's top ghost row: psi on the lanes and on the edge lanes' halo columns
+  C tg = (C)0;  // step A's top ghost row's psi
   if (wall_end) {
-    C f1[9], f2[9], r1, r2, h1, h2, p1, p2, hp1, hp2, g_rho;
+    C f1[9], f2[9], r1, r2, p1, p2, g_rho;
     bool dm;
-    produce(ny - 2, f1, r1, p1, h1, hp1, dm);
-    produce(ny - 3, f2, r2, p2, h2, hp2, dm);
-    ghostA(1, ny - 2, r1, r2, h1, h2, g_rho, tg, thg);
+    produce(ny - 2, f1, r1, p1, dm);
+    produce(ny - 3, f2, r2, p2, dm);
+    ghostA(1, ny - 2, r1, r2, g_rho, tg);
   }
   // window: rows (b, c, a) = (y - 1, y, y + 1) when step A processes row y
   C fc[9], fn[9], fp[9];
   C rb, rc, ra, pb, pc, pa, pbL, pbR, pcL, pcR, paL, paR;
   {
-    C hpb, hpc, hpa, hrb, hrc, hra;
     bool dm;
     if (wall_start) {
-      produce(ya0, fc, rc, pc, hrc, hpc, dm);
-      produce(ya0 + 1, fn, ra, pa, hra, hpa, dm);
-      ghostA(0, ya0, rc, ra, hrc, hra, rb, pb, hpb);
+      produce(ya0, fc, rc, pc, dm);
+      produce(ya0 + 1, fn, ra, pa, dm);
+      ghostA(0, ya0, rc, ra, rb, pb);
     } else {
       C fb[9];
-      produce(ya0 - 1, fb, rb, pb, hrb, hpb, dm);
-      produce(ya0, fc, rc, pc, hrc, hpc, dm);
-      if (ya0 + 1 <= ny - 2) produce(ya0 + 1, fn, ra, pa, hra, hpa, dm);
+      produce(ya0 - 1, fb, rb, pb, dm);
+      produce(ya0, fc, rc, pc, dm);
+      if (ya0 + 1 <= ny - 2) produce(ya0 + 1, fn, ra, pa, dm);
     }
-    xchg(pb, hpb, pbL, pbR);
-    xchg(pc, hpc, pcL, pcR);
+    xchg(pb, pbL, pbR);
+    xchg(pc, pcL, pcR);
     if (ya0 + 1 <= ny - 2) {
-      xchg(pa, hpa, paL, paR);
+      xchg(pa, paL, paR);
     } else {
       pa = tg;
-      xchg(tg, thg, paL, paR);
+      xchg(tg, paL, paR);
     }
   }
   // rows gathered by step A: ya0 - 1 .. ya1 + 1 within the fluid rows; the populations of row y + 2 are in flight
@@ -258,12 +244,6 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
 #pragma unroll
   for (int i = 0; i < 9; ++i) fp[i] = (C)0;
   if (ya0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ya0 + 2, fp);
-  // the halo column of the edge lanes, prefetched like fp by every lane of the waves that hold an edge lane
-  const bool wedge = wv == 0 || wv == (bwA - 1) / WAVE;
-  C hp[9], hn[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) hp[i] = (C)0;
-  if (wedge && ya0 + 2 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ya0 + 2, hp);
 
   // ---------------------------------------------------------------------------------------------- step B state
   const bool wallB_bot = y0 == 1, wallB_top = ylast == ny - 2;
@@ -279,7 +259,7 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
   const int yend = ylast + 2;
   auto row = [&](const int y) -> bool {
     // ---- step A: collide row y into the ring, then bring row y + 2 into the window
-    if (y <= ya1 && act) {
+    if (y <= ya1 && actA) {
       C fs[9];
       force_collide(y, fc, rc, pc, pcL, pcR, pb, pbL, pbR, pa, paL, paR, fs);
       const int s = y % 3;
@@ -289,26 +269,20 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : 1))
     rb = rc; pb = pc; pbL = pcL; pbR = pcR;
     rc = ra; pc = pa;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) { fc[i] = fn[i]; fn[i] = fp[i]; hn[i] = hp[i]; }
+    for (int i = 0; i < 9; ++i) { fc[i] = fn[i]; fn[i] = fp[i]; }
     const int ynew = y + 2;
     if (y < ya1 && ynew <= ny - 2) {
-      // densities of the rows prefetched an iteration ago, then the next prefetch
+      // densities of the row prefetched an iteration ago, then the next prefetch
       ra = rho0 + sum9(fn);
-      const C hra = rho0 + sum9(hn);
-      if (ynew + 1 <= yread) {
-        gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + 1, fp);
-        if (wedge) gather<S, C>(gin, plane, pitch, nx, ny, hcol, ynew + 1, hp);
-      }
+      if (ynew + 1 <= yread) gather<S, C>(gin, plane, pitch, nx, ny, col, ynew + 1, fp);
       bool dm;
       pa = node_psi<MIX>(d, ra, dm);
-      C hpa = (C)0;
-      if (edge) hpa = node_psi<MIX>(d, hra, dm);
-      xput(pa, hpa);
+      xput(pa);
     } else {
       // the row above the top fluid row is the ghost row (or step A is done and the window is no longer read)
       ra = (C)0;
       pa = tg;
-      xput(tg, thg);
+      xput(tg);
     }
     pcL = paL; pcR = paR;
     __syncthreads();  // step A's row y is in the ring; the psi of row y + 2 is in xa
