@@ -39,8 +39,8 @@ TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "traffic_step2_f64_c3.json")
 # this script (FETCH_SIZE, then WRITE_SIZE) by `bench.py --traffic-summary <name>`
 TRAFFIC_SPECS = {
     "step2_f32_c3": dict(
-        match="k_step2<float, 4, false, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
-        desc="k_step2<W=4> (two time steps per launch; FP32 storage shifted by rho_v, FP32 arithmetic with the FP64 "
+        match="k_step2<float, 8, false, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        desc="k_step2<W=8> (two time steps per launch; FP32 storage shifted by rho_v, FP32 arithmetic with the FP64 "
              "EOS in the vapour, tau = 1 BGK, geometric walls), 4096x2048 lattice, T = 0.5 T_c, theta = 45 deg, "
              "65 droplets; default shape"),
     "step2_mixed_c3": dict(
@@ -504,6 +504,7 @@ def main():
     ms, stable = timed_steps(sim, args.steps)
     diag = sim.diag()
     theta = sim.measure_contact_angle((1700, 2400, 1, 200), wall=0)
+    waves2 = sim.tuning()["waves2"]  # wavefronts per block of the two-step kernel the run used
     sim.close()
     nodes = case.fluid_nodes
     ms_step = ms / args.steps
@@ -545,8 +546,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
             # current), traffic_gbs those bytes over this run's time per launch
-            "kernel": f"k_step2<{'double' if f64 else 'float'}, 4, {'true' if mixed else 'false'}, false> (two time "
-                      "steps per launch)", "steps_per_launch": 2,
+            "kernel": f"k_step2<{'double' if f64 else 'float'}, {waves2}, {'true' if mixed else 'false'}, false> (two "
+                      "time steps per launch)", "steps_per_launch": 2,
             "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic

@@ -226,6 +226,13 @@ constexpr bool kDefaultPrefetch64 = false;
 constexpr int kMinDefaultStripRows = 2;
 // Two-step kernel (lbm_step2.hip): wavefronts per block and output rows per strip.
 constexpr int kDefaultWaves2 = 4;
+// FP32 arithmetic on contexts of at least this many fluid nodes: eight wavefronts per two-step block (504-column
+// tiles: fewer halo lanes and task prologues per output; 4096 x 2048: 107.2 against 103.2 GLUPS, 6144 x 3072 118.0
+// against 107.5); below it the wider tiles leave more of the last tile empty (3072 x 1536: 98.6 against 101.2,
+// 2048 x 1024: 81.9 against 86.1). The mixed form, FP64 and the general instance (one block of eight per compute
+// unit at its register use) keep four (4096 x 2048: 87.6 against 93.7, 44.9 against 56.7, 67.3 against 81.8).
+constexpr double kWide2MinNodes = 6.0e6;
+constexpr int kWide2MinNx = 2048;  // and instances at least four tiles of 504 columns wide
 constexpr int kDefaultStripRows2 = 32;
 constexpr int kMinStripRows2 = 8, kMaxStripRows2 = 256;  // bounds of the default from the occupancy
 // FP64 storage: at most 24 output rows per strip. At two blocks per compute unit the FP64 kernel runs faster with
@@ -611,6 +618,13 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     double nodes = 0;
     for (int i = 0; i < n_inst; ++i) nodes += (double)p[i].nx * (p[i].ny - 2);
     c->step2 = nodes >= kStep2MinNodes;
+    int min_nx = p[0].nx;
+    bool special = true;  // every instance takes the tau = 1 BGK specialisation (see tau1)
+    for (int i = 0; i < n_inst; ++i) {
+      min_nx = std::min(min_nx, p[i].nx);
+      special = special && p[i].tau == 1.0 && !uses_mrt(p[i]) && p[i].boundary == LBM_WALLS_Y;
+    }
+    if (c->storage == STORE_F32 && special && nodes >= kWide2MinNodes && min_nx >= kWide2MinNx) c->waves2 = 8;
   }
   if (p[0].step_variant > 0 && p[0].step_variant <= 2 * kNumWaveChoices) {
     c->waves = kWaveChoices[(p[0].step_variant - 1) % kNumWaveChoices];
