@@ -537,7 +537,7 @@ struct lbm_ctx {
     build_tasks2();
   }
 
-  // Two-step tiles: ceil(nx / (64 waves2 - 6)) column tiles of balanced width, rows balanced over
+  // Two-step tiles: ceil(nx / (64 waves2 - 8)) column tiles of balanced width, rows balanced over
   // ceil((ny-2)/strip_rows2) bands; bands outer, tiles inner (the kernel hands contiguous runs of this table to
   // one XCD each).
   void build_tasks2() {
