@@ -229,8 +229,8 @@ constexpr int kDefaultWaves2 = 4;
 // FP32 arithmetic on contexts of at least this many fluid nodes: eight wavefronts per two-step block (504-column
 // tiles: fewer halo lanes and task prologues per output; 4096 x 2048: 107.2 against 103.2 GLUPS, 6144 x 3072 118.0
 // against 107.5); below it the wider tiles leave more of the last tile empty (3072 x 1536: 98.6 against 101.2,
-// 2048 x 1024: 81.9 against 86.1). The mixed form, FP64 and the general instance (one block of eight per compute
-// unit at its register use) keep four (4096 x 2048: 87.6 against 93.7, 44.9 against 56.7, 67.3 against 81.8).
+// 2048 x 1024: 81.9 against 86.1). The mixed form, FP64 and the general instance keep four (4096 x 2048: 87.6
+// against 93.7, 44.9 against 56.7, 82.6 against 84.7).
 constexpr double kWide2MinNodes = 6.0e6;
 constexpr int kWide2MinNx = 2048;  // and instances at least four tiles of 504 columns wide
 constexpr int kDefaultStripRows2 = 32;
