@@ -54,7 +54,7 @@ TRAFFIC_SPECS = {
         desc="k_step2<double, W=4> (two time steps per launch in FP64: storage and arithmetic), same lattice; "
              "strips of at most 24 output rows"),
     "step2_f32_batched_c4": dict(
-        match="k_step2<float, ", exclude=", true", workload="c4", args="--batched-only --steps 40",
+        match="k_step2<float, ", exclude=", true", workload="c4", args="--batched-only --steps 40", last=10,
         desc="k_step2 (two time steps per launch, the autotuner's block shape) over the 256-instance batch (sizes "
              "64x32 .. 512x256, T/T_c in [0.6, 0.9], theta in [20, 160] deg, seed 1501), FP32 shifted by rho_v"),
     "step2_general_paper_setting_c3": dict(
@@ -78,8 +78,15 @@ def traffic_summary(name):
         path = os.path.join(ROOT, "gpurun_out", f"prof_{name}_{tag}", "p_counter_collection.csv")
         with open(path) as f:
             rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
-        kern = [float(r["Counter_Value"]) for r in rows
-                if spec["match"] in r["Kernel_Name"] and not (spec.get("exclude") and spec["exclude"] in r["Kernel_Name"])]
+        sel = [r for r in rows
+               if spec["match"] in r["Kernel_Name"] and not (spec.get("exclude") and spec["exclude"] in r["Kernel_Name"])]
+        if spec.get("last"):
+            # the timed launches only: the last ones of the shape the run ended with (an autotuned run first times
+            # other shapes, whose traffic differs)
+            sel.sort(key=lambda r: int(r["Dispatch_Id"]))
+            final = sel[-1]["Kernel_Name"]
+            sel = [r for r in sel if r["Kernel_Name"] == final][-spec["last"]:]
+        kern = [float(r["Counter_Value"]) for r in sel]
         copy = [float(r["Counter_Value"]) for r in rows if COPY_KERNEL in r["Kernel_Name"]]
         runs[counter] = (sum(kern) / len(kern), len(kern), sum(copy) / len(copy) if copy else None)
     if spec["workload"] == "c3":

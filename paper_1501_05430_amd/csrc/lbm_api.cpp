@@ -239,11 +239,11 @@ constexpr int kMinStripRows2 = 8, kMaxStripRows2 = 256;  // bounds of the defaul
 // several rounds of 24-row strips than with one round of taller ones (4096 x 2048: 45.7 against 34.0 GLUPS); FP32
 // loses a quarter of its rate to a partial second round, so it keeps the one-round rule.
 constexpr int kMaxStripRows2F64 = 24;
-// Below about 7.5e5 fluid nodes per context the two-step kernel has too few tasks to pay for its halo: one-step
-// launches are as fast or faster (200 x 100: 1.8 against 1.2 GLUPS; 512 x 256: 10.3 against 7.7; 1024 x 512: 29.7
-// against 27.7 in FP32), above it two steps per launch win (1448 x 724: 46.8 against 32.2, FP64 40.7 against 25.8;
-// 2048 x 1024: 68.8 against 61.5; 4096 x 2048: 92.4 against 65, FP64 50.3 against 34.9).
-constexpr double kStep2MinNodes = 750000.0;
+// Below about 2e5 fluid nodes per context the two-step kernel has too few tasks to pay for its halo: one-step
+// launches are as fast or faster (200 x 100: 1.8 against 1.2 GLUPS; 512 x 256: 10.4 against 10.0 in FP32, 9.3
+// against 9.8 in FP64), above it two steps per launch win (724 x 362: 18.6 against 16.0, FP64 17.8 against 13.6;
+// 1024 x 512: 34.9 against 30.1, FP64 27.7 against 21.9; 4096 x 2048: 106.6 against 65, FP64 56.0 against 34.9).
+constexpr double kStep2MinNodes = 200000.0;
 constexpr int kStep2Halo = 8;  // lanes beyond a two-step tile's outputs (three of step A and one of psi per side)
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;

@@ -236,7 +236,7 @@ def test_two_step_equals_one_step_over_a_long_run(precision):
     bit for bit at every 1000 steps (each kernel inlines the same node arithmetic, whose rounding is spelled out)."""
     case = W.c2_angle(90.0)
     one = gpu_sim(case, precision=precision, step_variant=5)
-    two = gpu_sim(case, precision=precision, step_variant=11)  # the default below 750 000 nodes is one step
+    two = gpu_sim(case, precision=precision, step_variant=11)  # forced: the comparison must not rest on the default
     for _ in range(4):
         one.step(1000)
         two.step(1000)
