@@ -29,14 +29,19 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # the dominant kernel: the two-step FP32 kernel (two time steps per launch) and the headers it inlines
 KERNEL_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
               for n in ("lbm_step2.hip", "lbm_device.h", "lbm_internal.h")]
+ADJOINT_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
+               for n in ("lbm_adjoint.hip", "lbm_device.h", "lbm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")
 TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step2_f32_batched_c4.json")
 TRAFFIC_FILE_MIXED = os.path.join(ROOT, "profiles", "traffic_step2_mixed_c3.json")
+TRAFFIC_FILE_ADJ = {"f64": os.path.join(ROOT, "profiles", "traffic_adjoint_f64_c3.json"),
+                    "f32": os.path.join(ROOT, "profiles", "traffic_adjoint_f32_c3.json")}
 TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "traffic_step2_f64_c3.json")
 
 
-# HBM-traffic summaries of the step kernel (profiles/traffic_<name>.json), made from two rocprofv3 counter runs of
-# this script (FETCH_SIZE, then WRITE_SIZE) by `bench.py --traffic-summary <name>`
+# HBM-traffic summaries of the step kernels and of the adjoint's fused pass (profiles/traffic_<name>.json), made
+# from two rocprofv3 counter runs of this script (FETCH_SIZE, then WRITE_SIZE) by `bench.py --traffic-summary <name>`;
+# `run` names the counter runs when two summaries share them, `steps` the time steps per launch (default 2)
 TRAFFIC_SPECS = {
     "step2_f32_c3": dict(
         match="k_step2<float, 8, false, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
@@ -61,6 +66,17 @@ TRAFFIC_SPECS = {
         match="k_step2<float, 4, false, true>", workload="c3", args="--paper-setting-only --steps 20",
         desc="k_step2<float, W=4, general collision> in the paper's setting (piecewise-linear EOS at a density ratio "
              "of 1000, kappa = 0.5, MRT with diag(0,1,...,1)), same lattice, FP32 shifted by rho_v"),
+    "adjoint_f64_c3": dict(
+        match="ka_fused<false, double>", workload="c3", run="adjoint_c3", args="--adjoint-only", steps=1,
+        bytes_per_update=216, state_elem=8, sources="adjoint",
+        desc="ka_fused<BGK, FP64 storage> (the adjoint step's fused reverse pass: transposed streaming, collision, "
+             "force and psi; f_n and lambda_{n+1} read, lambda_n written), 4096x2048 lattice after 20 steps of the "
+             "droplet workload, a seeded random cotangent"),
+    "adjoint_f32_c3": dict(
+        match="ka_fused<false, float>", workload="c3", run="adjoint_c3", args="--adjoint-only", steps=1,
+        bytes_per_update=108, state_elem=4, sources="adjoint",
+        desc="ka_fused<BGK, FP32 storage> (lbm_adjoint_step_f32: state and adjoints stored in FP32, FP64 "
+             "arithmetic), same lattice and cotangent"),
 }
 COPY_KERNEL = "k_copy<HIP_vector_type<float, 4u> >"
 
@@ -73,9 +89,12 @@ def traffic_summary(name):
     import csv
     from paper_1501_05430_amd import workloads as W
     spec = TRAFFIC_SPECS[name]
+    run = spec.get("run", name)
+    sources = ADJOINT_SRC if spec.get("sources") == "adjoint" else KERNEL_SRC
+    steps = spec.get("steps", 2)
     runs = {}
     for counter, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        path = os.path.join(ROOT, "gpurun_out", f"prof_{name}_{tag}", "p_counter_collection.csv")
+        path = os.path.join(ROOT, "gpurun_out", f"prof_{run}_{tag}", "p_counter_collection.csv")
         with open(path) as f:
             rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
         sel = [r for r in rows
@@ -94,7 +113,10 @@ def traffic_summary(name):
         nodes = case.fluid_nodes
         pitch = (case.nx + 63) // 64 * 64
         copy_bytes = 4 * 9 * (case.ny - 2) * pitch    # the probe copies an FP32 state of this lattice
-        state_bytes = spec.get("bytes_per_update", 72) // 18 * 9 * (case.ny - 2) * pitch   # the kernel's own state
+        if spec.get("state_elem"):   # the adjoint's arrays: [9][ny-2][nx], unpadded
+            state_bytes = spec["state_elem"] * 9 * (case.ny - 2) * case.nx
+        else:
+            state_bytes = spec.get("bytes_per_update", 72) // 18 * 9 * (case.ny - 2) * pitch   # the kernel's own state
     else:
         nodes = sum(c.fluid_nodes for c in W.c4_batch())
         copy_bytes = state_bytes = None
@@ -110,19 +132,19 @@ def traffic_summary(name):
         calib["kernel"] += " (taken from the step2_f32_c3 run)"
     rd = runs["FETCH_SIZE"][0] * 1024 * calib["fetch_scale"]
     wr = runs["WRITE_SIZE"][0] * 1024 * calib["write_scale"]
-    alg = 2 * spec.get("bytes_per_update", 72) * nodes
+    alg = steps * spec.get("bytes_per_update", 72) * nodes
     out = {
         "kernel": spec["desc"],
-        "kernel_source_sha256": kernel_sha(),
-        "kernel_sources": [os.path.relpath(p_, ROOT) for p_ in KERNEL_SRC],
-        "commands": [f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof_{name}_{t} -o p -- python3 bench.py "
+        "kernel_source_sha256": kernel_sha(sources),
+        "kernel_sources": [os.path.relpath(p_, ROOT) for p_ in sources],
+        "commands": [f"rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof_{run}_{t} -o p -- python3 bench.py "
                      f"{spec['args']}" for c, t in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))]
                     + [f"python3 bench.py --traffic-summary {name}"],
         "calibration": calib,
         "kernel_counters_kib_per_launch": {"FETCH_SIZE": round(runs["FETCH_SIZE"][0], 1),
                                            "WRITE_SIZE": round(runs["WRITE_SIZE"][0], 1),
                                            "launches_averaged": runs["FETCH_SIZE"][1]},
-        "time_steps_per_launch": 2,
+        "time_steps_per_launch": steps,
         "hbm_read_bytes_per_launch": int(rd),
         "hbm_write_bytes_per_launch": int(wr),
         "hbm_bytes_per_launch": int(rd + wr),
@@ -138,23 +160,24 @@ def traffic_summary(name):
     print(json.dumps({"wrote": os.path.relpath(dst, ROOT), "traffic_over_algorithmic": out["traffic_over_algorithmic"]}))
 
 
-def kernel_sha():
-    """Hash of the step kernel's sources: traffic counters taken from another version are not reported."""
+def kernel_sha(sources=None):
+    """Hash of a kernel's sources (the step kernel's by default): traffic counters taken from another version are
+    not reported."""
     h = hashlib.sha256()
-    for path in KERNEL_SRC:
+    for path in sources or KERNEL_SRC:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def profile_traffic(path):
+def profile_traffic(path, sources=None):
     """(HBM bytes per launch, time steps per launch) from a committed counter summary, if it was taken on the current
     sources of the kernel; (None, 1) otherwise."""
     if not os.path.exists(path):
         return None, 1
     with open(path) as f:
         tr = json.load(f)
-    if tr.get("kernel_source_sha256") != kernel_sha():
+    if tr.get("kernel_source_sha256") != kernel_sha(sources):
         return None, 1
     return tr.get("hbm_bytes_per_launch"), tr.get("time_steps_per_launch", 1)
 
@@ -396,8 +419,12 @@ def adjoint_rate(case, calls=30, dtype="f64", **kw):
     finite = bool(torch.isfinite(lam0).all().item())
     sim.close()
     nbytes = 216 if dtype == "f64" else 108
-    return {"ms_per_step": round(ms, 4), "mlups": round(case.fluid_nodes / ms / 1e3, 1),
-            "gbs_alg": round(nbytes * case.fluid_nodes / ms / 1e6, 1), "finite": finite}
+    out = {"ms_per_step": round(ms, 4), "mlups": round(case.fluid_nodes / ms / 1e3, 1),
+           "gbs_alg": round(nbytes * case.fluid_nodes / ms / 1e6, 1), "finite": finite}
+    if not kw and case.nx == 4096 and case.ny == 2048:
+        # the fused pass's measured HBM bytes per launch (committed counter summary of this lattice), if current
+        out["fused_pass_traffic"] = profile_traffic(TRAFFIC_FILE_ADJ[dtype], ADJOINT_SRC)[0]
+    return out
 
 
 def piecewise_rate(case, steps=2000, kappa=0.0):
