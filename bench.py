@@ -44,17 +44,17 @@ TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "traffic_step2_f64_c3.json")
 # `run` names the counter runs when two summaries share them, `steps` the time steps per launch (default 2)
 TRAFFIC_SPECS = {
     "step2_f32_c3": dict(
-        match="k_step2<float, 8, false, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+        match="k_step2<float, 8, false, false, false>", workload="c3", args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<W=8> (two time steps per launch; FP32 storage shifted by rho_v, FP32 arithmetic with the FP64 "
              "EOS in the vapour, tau = 1 BGK, geometric walls), 4096x2048 lattice, T = 0.5 T_c, theta = 45 deg, "
              "65 droplets; default shape"),
     "step2_mixed_c3": dict(
-        match="k_step2<float, 4, true, false>", workload="c3",
+        match="k_step2<float, 4, true, false, false>", workload="c3",
         args="--precision f32_shifted_mixed --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<W=4> in the mixed form (FP32 storage shifted by rho_v and FP32 sums; psi, force, equilibrium "
              "and forcing in FP64), same lattice and shape"),
     "step2_f64_c3": dict(
-        match="k_step2<double, 4, false, false>", workload="c3", bytes_per_update=144,
+        match="k_step2<double, 4, false, false, false>", workload="c3", bytes_per_update=144,
         args="--precision f64 --steps 20 --warmup 5 --no-extras --no-cpu-baseline",
         desc="k_step2<double, W=4> (two time steps per launch in FP64: storage and arithmetic), same lattice; "
              "strips of at most 24 output rows"),
@@ -63,7 +63,7 @@ TRAFFIC_SPECS = {
         desc="k_step2 (two time steps per launch, the autotuner's block shape) over the 256-instance batch (sizes "
              "64x32 .. 512x256, T/T_c in [0.6, 0.9], theta in [20, 160] deg, seed 1501), FP32 shifted by rho_v"),
     "step2_general_paper_setting_c3": dict(
-        match="k_step2<float, 4, false, true>", workload="c3", args="--paper-setting-only --steps 20",
+        match="k_step2<float, 4, false, true, false>", workload="c3", args="--paper-setting-only --steps 20",
         desc="k_step2<float, W=4, general collision> in the paper's setting (piecewise-linear EOS at a density ratio "
              "of 1000, kappa = 0.5, MRT with diag(0,1,...,1)), same lattice, FP32 shifted by rho_v"),
     "adjoint_f64_c3": dict(
@@ -580,8 +580,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
             # current), traffic_gbs those bytes over this run's time per launch
-            "kernel": f"k_step2<{'double' if f64 else 'float'}, {waves2}, {'true' if mixed else 'false'}, false> (two "
-                      "time steps per launch)", "steps_per_launch": 2,
+            "kernel": f"k_step2<{'double' if f64 else 'float'}, {waves2}, {'true' if mixed else 'false'}, false, false> "
+                      "(two time steps per launch; one launch in 50 its checked instance)", "steps_per_launch": 2,
             "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic

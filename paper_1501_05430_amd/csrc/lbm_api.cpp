@@ -264,7 +264,7 @@ struct Inst {
 };
 
 struct Layout {
-  size_t desc, tasks, wdiag, first, idiag, drops, rho_scratch, partials, tasks2, total;
+  size_t desc, tasks, wdiag, first, first2, idiag, drops, rho_scratch, partials, tasks2, total;
   size_t task_cap, task2_cap;
   std::vector<size_t> inst_f[2], inst_th, inst_ghost, inst_adj;
 };
@@ -358,8 +358,9 @@ Layout make_layout(const lbm_params* p, int32_t n) {
   }
   L.desc = take(sizeof(InstDesc) * n);
   L.tasks = take(sizeof(WaveTask) * L.task_cap);
-  L.wdiag = take(sizeof(WaveDiag) * L.task_cap);
+  L.wdiag = take(sizeof(WaveDiag) * std::max(L.task_cap, L.task2_cap));  // per task of either table
   L.first = take(sizeof(int32_t) * (n + 1));
+  L.first2 = take(sizeof(int32_t) * (n + 1));
   L.idiag = take(sizeof(InstDiag) * n);
   L.drops = take(sizeof(double) * 3 * kMaxDrops);
   L.rho_scratch = take(sizeof(double) * max_nodes);
@@ -472,6 +473,7 @@ struct lbm_ctx {
   WaveTask* d_tasks2() { return (WaveTask*)(ws + L.tasks2); }
   WaveDiag* d_wdiag() { return (WaveDiag*)(ws + L.wdiag); }
   int32_t* d_first() { return (int32_t*)(ws + L.first); }
+  int32_t* d_first2() { return (int32_t*)(ws + L.first2); }
   InstDiag* d_idiag() { return (InstDiag*)(ws + L.idiag); }
   double* d_partials() { return (double*)(ws + L.partials); }
   double* d_rho_scratch() { return (double*)(ws + L.rho_scratch); }
@@ -573,6 +575,8 @@ struct lbm_ctx {
       HIP_TRY(hipMemcpyAsync(d_tasks2(), tasks2.data(), sizeof(WaveTask) * tasks2.size(), hipMemcpyHostToDevice,
                              stream));
     HIP_TRY(hipMemcpyAsync(d_first(), first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_first2(), first2.data(), sizeof(int32_t) * first2.size(), hipMemcpyHostToDevice,
+                           stream));
     HIP_TRY(hipMemcpyAsync(d_desc(), hdesc.data(), sizeof(InstDesc) * hdesc.size(), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     return LBM_OK;
@@ -883,10 +887,11 @@ int lbm_apply_wetting(lbm_ctx* c, int32_t inst, const double* theta_bottom, cons
 namespace {
 
 // Queue `count` steps for the selection (task range), buffer flips starting at 0, checks every K (0 = none)
-// counting from the first queued step, plus one after the last step if final_check. Two unchecked steps in a row
-// go into one two-step launch where the selection allows it; checked steps are one-step launches (the check reads
-// the launch's input state). Each launch flips the buffers once. *launches receives the launch count; dry = true
-// only counts.
+// counting from the first queued step, plus one after the last step if final_check. A check reads the input state
+// of its step. Where the selection allows it, an unchecked step and the step after it go into one two-step launch,
+// which takes the second step's check if it has one (its input is the state after the first); a checked step not
+// paired that way is a one-step launch. Each launch flips the buffers once. *launches receives the launch count;
+// dry = true only counts.
 int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check, int64_t* launches, bool dry = false) {
   const int a = sel < 0 ? 0 : c->first[sel];
   const int b = sel < 0 ? c->first[c->n()] : c->first[sel + 1];
@@ -899,10 +904,15 @@ int queue_steps(lbm_ctx* c, int sel, int64_t count, int K, bool final_check, int
   int64_t nl = 0;
   for (int64_t i = 0; i < count; ++nl) {
     const bool chk = chk_at(i);
-    if (two && !chk && i + 1 < count && !chk_at(i + 1)) {
-      if (!dry)
+    if (two && !chk && i + 1 < count) {
+      const bool chk2 = chk_at(i + 1);
+      if (!dry) {
         HIP_TRY(launch_step2(c->d_desc(), c->d_tasks2() + a2, b2 - a2, c->waves2, c->storage, !c->tau1(sel),
-                             (int)(nl & 1), c->stream));
+                             (int)(nl & 1), c->stream, chk2 ? c->d_wdiag() + a2 : nullptr));
+        if (chk2)
+          HIP_TRY(launch_finalize_diag(c->d_tasks2(), c->d_first2(), ninst, inst0, c->d_wdiag(), c->d_idiag(),
+                                       c->d_desc(), c->stream));
+      }
       i += 2;
       continue;
     }

@@ -72,8 +72,10 @@ hipError_t launch_step(int storage, bool check, bool tau1, int waves, bool prefe
 // any tau). Tasks are tiles: output columns [x0, x0 + width) with width <= 64 waves - 8 (the kernel adds four halo
 // lanes per side), output rows [y0, y0 + nrows). Reads buffer cur ^ flip, writes the other one (as one one-step
 // launch). storage: STORE_F64, STORE_F32 or STORE_F32M (the mixed arithmetic of LBM_F32_SHIFTED_MIXED).
+// d_wdiag (one entry per task) makes it a checked launch: the diagnostics of the second step's input state, which
+// k_finalize_diag then folds per instance over the two-step task ranges.
 hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage,
-                        bool general, int flip, hipStream_t s);
+                        bool general, int flip, hipStream_t s, WaveDiag* d_wdiag = nullptr);
 // Resident blocks of the two-step kernel per compute unit (hipOccupancyMaxActiveBlocksPerMultiprocessor).
 hipError_t step2_blocks_per_cu(int waves, int storage, bool general, int* blocks);
 hipError_t launch_finalize_diag(const WaveTask* d_tasks, const int32_t* d_inst_first, int ninst_sel, int inst0,

@@ -41,10 +41,14 @@ constexpr int kXcds = 8;
 
 // FP64: at least two blocks per compute unit, which caps the registers at 256 (two wavefronts per SIMD; the ring of
 // FP64 rows allows two blocks of four wavefronts per compute unit). The general FP32 instance: four wavefronts per
-// SIMD (128 registers, a few spilled), which runs the paper's setting 3.6 % faster than three at 140 registers.
-template <class S, int W, bool MIX, bool GEN>
-__global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : ((GEN && !MIX) ? 4 : 1))) void k_step2(const InstDesc* __restrict__ descs,
-                                                    const WaveTask* __restrict__ tasks, int ntasks, int flip) {
+// SIMD (128 registers, a few spilled), which runs the paper's setting 3.6 % faster than three at 140 registers. The
+// checked mixed instance is held to the four wavefronts per SIMD of the unchecked one, whose task table it runs.
+template <class S, int W, bool MIX, bool GEN, bool CHK>
+__global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value
+                                            ? 2
+                                            : (((GEN && !MIX) || (MIX && !GEN && CHK)) ? 4 : 1))) void k_step2(const InstDesc* __restrict__ descs,
+                                                    const WaveTask* __restrict__ tasks, int ntasks, int flip,
+                                                    WaveDiag* __restrict__ wdiag) {
   typedef typename ComputeOf<S>::type C;
   typedef typename Gbl<S>::T GS;
   static_assert(!MIX || std::is_same<S, float>::value, "the mixed arithmetic is a form of FP32 storage");
@@ -91,6 +95,16 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : ((G
   __shared__ C xa[2][L + 2];
   __shared__ C psB[3][L];
   __shared__ C rhB[2][L];
+  // CHK: a checked launch also takes the diagnostics of step B's input, the state after step A, which is what a
+  // checked one-step launch of the second step reads: mass, non-finite densities, psi clamps (output nodes) and
+  // ghost-row clamps (output columns). Each output lane sums its own nodes here; the block folds them at the end
+  // into wdiag[task].
+  __shared__ double ckm[CHK ? L : 1];
+  __shared__ int ckc[3][CHK ? L : 1];
+  if constexpr (CHK) {
+    ckm[lx] = 0.0;
+    ckc[0][lx] = ckc[1][lx] = ckc[2][lx] = 0;
+  }
 
   // (left, right) neighbours of a per-lane value through xa: put, barrier, get (lanes 1 .. bwA read them)
   int par = 0;
@@ -310,6 +324,14 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : ((G
       psB[sc][lx] = node_psi<MIX>(d, rj, dm);
       if (bot) rhB[0][lx] = rj;
       if (top) rhB[1][lx] = rj;
+      if constexpr (CHK) if (actBc && j >= y0 && j <= ylast) {
+        double mm = (double)fg[0];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) mm += (double)fg[i];
+        ckm[lx] += mm + d.rho0;
+        ckc[0][lx] += isfinite(rj) ? 0 : 1;
+        ckc[1][lx] += dm ? 1 : 0;
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) fg[i] = __builtin_nondeterministic_value((C)0);  // never collided
@@ -324,6 +346,7 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : ((G
         const double r0 = ghost_density((double)rhB[0][lx - 1], (double)rhB[0][lx + 1], (double)rhB[0][lx],
                                         (double)rj, cos_th[col], cot_th[col], iters, d.rho_cap_hi, gc);
         psB[0][lx] = (C)psi_eval(d, r0, dm);
+        if constexpr (CHK) if (gc && actBc) ckc[2][lx] += 1;
       }
     }
     // top ghost row (row ny - 1) after the last gather: row ny - 2's densities through LDS, row ny - 3's own
@@ -335,6 +358,7 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : ((G
         const double r0 = ghost_density((double)rhB[1][lx - 1], (double)rhB[1][lx + 1], (double)rhB[1][lx],
                                         (double)rBtop2, cos_th[nx + col], cot_th[nx + col], iters, d.rho_cap_hi, gc);
         psB[(ny - 1) % 3][lx] = (C)psi_eval(d, r0, dm);
+        if constexpr (CHK) if (gc && actBc) ckc[2][lx] += 1;
       }
     }
     __syncthreads();  // step B's psi of row j (and a ghost row) are in the ring
@@ -360,11 +384,36 @@ __global__ __launch_bounds__(WAVE * W, (std::is_same<S, double>::value ? 2 : ((G
     if (row(y + 1)) break;
     if (row(y + 2)) break;
   }
+  if constexpr (CHK) {  // fold in a fixed order: lanes of a wavefront, then the wavefronts
+    __shared__ double sm[W];
+    __shared__ int si[W][3];
+    const double m = wave_sum(ckm[lx]);
+    const int c0 = wave_sum(ckc[0][lx]), c1 = wave_sum(ckc[1][lx]), c2 = wave_sum(ckc[2][lx]);
+    if (lane == 0) {
+      sm[wv] = m;
+      si[wv][0] = c0;
+      si[wv][1] = c1;
+      si[wv][2] = c2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      WaveDiag w;
+      w.mass = 0.0;
+      w.nonfinite = w.psi_clamps = w.ghost_clamps = w.pad = 0;
+      for (int k = 0; k < W; ++k) {
+        w.mass += sm[k];
+        w.nonfinite += si[k][0];
+        w.psi_clamps += si[k][1];
+        w.ghost_clamps += si[k][2];
+      }
+      wdiag[task] = w;
+    }
+  }
 }
 
 template <class S, int W, bool MIX, bool GEN>
 int occupancy_of(int* blocks) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<S, W, MIX, GEN>, WAVE * W, 0);
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step2<S, W, MIX, GEN, false>, WAVE * W, 0);
 }
 
 template <class S, bool MIX, bool GEN>
@@ -377,15 +426,22 @@ hipError_t blocks_per_cu(int waves, int* blocks) {
   }
 }
 
-template <class S, bool MIX, bool GEN>
-void launch2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip, unsigned grid,
-             hipStream_t s) {
+template <class S, bool MIX, bool GEN, bool CHK>
+void launch2c(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip, WaveDiag* wd,
+              unsigned grid, hipStream_t s) {
   switch (waves) {
-    case 1: hipLaunchKernelGGL((k_step2<S, 1, MIX, GEN>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 2: hipLaunchKernelGGL((k_step2<S, 2, MIX, GEN>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    case 4: hipLaunchKernelGGL((k_step2<S, 4, MIX, GEN>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
-    default: hipLaunchKernelGGL((k_step2<S, 8, MIX, GEN>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip); break;
+    case 1: hipLaunchKernelGGL((k_step2<S, 1, MIX, GEN, CHK>), dim3(grid), dim3(WAVE), 0, s, d_desc, d_tasks, ntasks, flip, wd); break;
+    case 2: hipLaunchKernelGGL((k_step2<S, 2, MIX, GEN, CHK>), dim3(grid), dim3(2 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, wd); break;
+    case 4: hipLaunchKernelGGL((k_step2<S, 4, MIX, GEN, CHK>), dim3(grid), dim3(4 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, wd); break;
+    default: hipLaunchKernelGGL((k_step2<S, 8, MIX, GEN, CHK>), dim3(grid), dim3(8 * WAVE), 0, s, d_desc, d_tasks, ntasks, flip, wd); break;
   }
+}
+
+template <class S, bool MIX, bool GEN>
+void launch2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int flip, WaveDiag* wd,
+             unsigned grid, hipStream_t s) {
+  if (wd) launch2c<S, MIX, GEN, true>(d_desc, d_tasks, ntasks, waves, flip, wd, grid, s);
+  else launch2c<S, MIX, GEN, false>(d_desc, d_tasks, ntasks, waves, flip, wd, grid, s);
 }
 
 template <bool GEN>
@@ -397,10 +453,10 @@ hipError_t blocks_for(int waves, int storage, int* blocks) {
 
 template <bool GEN>
 void launch_for(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage, int flip,
-                unsigned grid, hipStream_t s) {
-  if (storage == STORE_F64) launch2<double, false, GEN>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
-  else if (storage == STORE_F32M) launch2<float, true, GEN>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
-  else launch2<float, false, GEN>(d_desc, d_tasks, ntasks, waves, flip, grid, s);
+                WaveDiag* wd, unsigned grid, hipStream_t s) {
+  if (storage == STORE_F64) launch2<double, false, GEN>(d_desc, d_tasks, ntasks, waves, flip, wd, grid, s);
+  else if (storage == STORE_F32M) launch2<float, true, GEN>(d_desc, d_tasks, ntasks, waves, flip, wd, grid, s);
+  else launch2<float, false, GEN>(d_desc, d_tasks, ntasks, waves, flip, wd, grid, s);
 }
 
 }  // namespace
@@ -411,11 +467,11 @@ hipError_t step2_blocks_per_cu(int waves, int storage, bool general, int* blocks
 }
 
 hipError_t launch_step2(const InstDesc* d_desc, const WaveTask* d_tasks, int ntasks, int waves, int storage,
-                        bool general, int flip, hipStream_t s) {
+                        bool general, int flip, hipStream_t s, WaveDiag* d_wdiag) {
   if (ntasks <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(((ntasks + kXcds - 1) / kXcds) * kXcds);
-  if (general) launch_for<true>(d_desc, d_tasks, ntasks, waves, storage, flip, grid, s);
-  else launch_for<false>(d_desc, d_tasks, ntasks, waves, storage, flip, grid, s);
+  if (general) launch_for<true>(d_desc, d_tasks, ntasks, waves, storage, flip, d_wdiag, grid, s);
+  else launch_for<false>(d_desc, d_tasks, ntasks, waves, storage, flip, d_wdiag, grid, s);
   return hipGetLastError();
 }
 

@@ -87,14 +87,41 @@ def test_two_step_options_bitwise(precision, kw):
 
 @pytest.mark.parametrize("check_every", [1, 3, 8, 100])
 def test_checked_steps_between_two_step_launches(check_every):
-    """Checked steps run as one-step launches (the check reads the launch's input); the state, the checks and the
-    mass they report match a run of one-step launches only (the mass up to the order of its sums)."""
+    """A check reads its step's input state: a checked step paired with the unchecked step before it is the second
+    step of a checked two-step launch, any other checked step a checked one-step launch. The state, the checks and
+    the mass they report match a run of one-step launches only (the mass up to the order of its sums)."""
     case = case_of(150, 40, 0.8, 60.0, 90.0, [(75, 0.5, 15.0)])
     a, b, d1, d2 = pair(case, 57, 11, check_every=check_every)
     assert np.array_equal(a, b)
     assert d1["checks"] == d2["checks"] > 0
     assert d2["mass"] == pytest.approx(d1["mass"], rel=1e-12)
     assert d2["nonfinite"] == d1["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("precision", ["f32_shifted", "f64"])
+@pytest.mark.parametrize("check_every,steps", [(2, 20), (5, 23)])
+def test_checked_two_step_launches_count_the_clamps(precision, check_every, steps):
+    """Checked two-step launches count what checked one-step launches count. A droplet started above the largest
+    density with real psi (0.5 against 0.458 at 0.85 T_c) makes psi clamp in the fluid and the ghost densities clamp
+    at the walls for the first steps; checks every 2 steps (each the second step of a two-step launch) and every 5
+    (odd positions: one-step and two-step checks alternate) give the same checks, psi clamps, ghost-row clamps and
+    non-finite counts as one-step launches, the mass up to the order of its sums, the state bit for bit."""
+    nx, ny = 96, 40
+    th = np.radians(np.linspace(40.0, 140.0, nx))
+    case = W.Case("s2_clamp", nx, ny, 0.85, th, th[::-1].copy(), [48.0], [0.5], [14.0], 0)
+    out = []
+    for variant in (5, 11):
+        sim = gpu_sim(case, precision=precision, step_variant=variant, check_every=check_every, init=False)
+        sim.init_droplet(case.xc, case.yc, case.R, rho_l=0.5)
+        sim.step(steps)
+        out.append((sim.populations(), sim.diag()))
+        sim.close()
+    (a, d1), (b, d2) = out
+    assert d1["psi_clamps"] > 0 and d1["ghost_clamps"] > 0, d1
+    assert np.array_equal(a, b)
+    for k in ("checks", "psi_clamps", "ghost_clamps", "nonfinite"):
+        assert d2[k] == d1[k], (k, d1, d2)
+    assert d2["mass"] == pytest.approx(d1["mass"], rel=1e-12)
 
 
 def test_graph_chunks_and_remainders_bitwise():
