@@ -180,10 +180,12 @@ int lbm_init_droplet(lbm_ctx* c, int32_t inst, int32_t n, const double* xc, cons
  * recomputed inside every lbm_step. Synchronizes the stream (the host arrays may be reused on return). */
 int lbm_apply_wetting(lbm_ctx* c, int32_t inst, const double* theta_bottom, const double* theta_top);
 
-/* Advance nsteps time steps. inst >= 0 steps one instance; inst = -1 steps every instance with one kernel launch
- * per step. Steps are replayed from a captured HIP graph in chunks when the stream is not the null stream.
- * With check_every > 0 a device check runs every check_every steps and after the last step; the call then
- * synchronizes the stream once at its end and returns LBM_E_UNSTABLE if a check saw a non-finite density. */
+/* Advance nsteps time steps. inst >= 0 steps one instance; inst = -1 steps every instance, each kernel launch
+ * covering all of them (two time steps per launch where step_variant allows it, see above). Steps are replayed from
+ * a captured HIP graph in chunks when the stream is not the null stream. With check_every > 0 a device check runs
+ * every check_every steps and after the last step, on the state its step starts from (inside a two-step launch when
+ * the step before it is unchecked); the call then synchronizes the stream once at its end and returns
+ * LBM_E_UNSTABLE if a check saw a non-finite density. */
 int lbm_step(lbm_ctx* c, int32_t inst, int64_t nsteps);
 
 /* lbm_step with device timing: HIP events on the context's stream bracket the queued steps (recorded before the
