@@ -93,8 +93,8 @@ def equal_area_radius(deg, R0=30.0):
 def test_angle_range_at_large_density_ratios(ratio, angles):
     """Figs. 6-8: with four iterates the geometric wall holds a range of angles at density ratios of 100 and 1000
     without losing stability (400 x 100, semicircle R = 30, 150 000 steps). Measured: 16.9 / 29.6 / 44.9 / 92.6 deg
-    at ratio 100 and 44.6 / 91.6 deg at ratio 1000 for the prescribed values, each within 3 deg (the survey's
-    acceptance). Fig. 8: the density next to the wall equals the bulk density (no near-wall layer). Obtuse angles
+    at ratio 100 and 44.6 / 91.6 deg at ratio 1000 for the prescribed values, each within 3 deg (the
+    acceptance bound of this test). Fig. 8: the density next to the wall equals the bulk density (no near-wall layer). Obtuse angles
     and the acute ones at ratio 1000 are in the tests below."""
     import paper_1501_05430_amd as P
     eos = PW100 if ratio == 100 else PW1000
