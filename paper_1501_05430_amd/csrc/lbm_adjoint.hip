@@ -19,7 +19,7 @@
 // in step 3; G_f_bar += Q_bar : Q / G_f); Martys-Chen walls (Eq. 14: psi_bar += +-(G_w/2) F_bar_y on the boundary
 // rows, no ghost rows to transpose); periodic rows (every neighbour a fluid row, no ghost rows).
 // Kinks (|T| of Eq. 19, the square root at 0, the clamps) take the sub-gradient 0.
-// Passes: ka_prep_rows and ka_ghost_fwd (forward values of the wall rows), ka_fused (steps 1-3 and 5 in one
+// Passes: ka_wall_fwd (forward values of the wall rows and the ghost rows), ka_fused (steps 1-3 and 5 in one
 // walk over row strips), ka_ghost_adj (step 4), ka_wall_fix (step 4's boundary-row terms into lambda_n),
 // ka_finalize (the G partials).
 #include <hip/hip_runtime.h>
@@ -108,50 +108,37 @@ __device__ inline void psi_dpsi(const InstDesc& d, double rho, double& psi, doub
   dps = (dp - 1.0 / 3.0) * d.two_over_Gpsi * h;  // (p' - 1/3) (2 / G_psi) / (2 psi)
 }
 
-// 1. forward density and psi of a fluid node from its populations (every pass of the reverse step uses these)
-__device__ inline void node_rho_psi(const InstDesc& d, const double (&fl)[9], double& r, double& p) {
-  r = sum9(fl);
-  double dps;
-  psi_dpsi(d, r, p, dps);
-}
-
+// 1. forward density of a fluid node from its populations
 template <class T>
-__device__ inline void prep_node(const InstDesc& d, const T* __restrict__ f, int64_t n, int nx, int x, int y,
-                                 AdjScratch& sc) {
+__device__ inline double node_rho(const T* __restrict__ f, int64_t n, int nx, int x, int y) {
   const unsigned k = (unsigned)((y - 1) * nx + x);  // node counts are below 2^31 (lbm_create checks)
   double fl[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) fl[i] = (double)f[i * n + k];
-  double r, p;
-  node_rho_psi(d, fl, r, p);
-  Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
-  R.at(x, y) = r;
-  P.at(x, y) = p;
+  return sum9(fl);
 }
 
-// density and psi into the scratch field of the four wall-adjacent rows (read by the ghost rows and their adjoint)
+// Forward values of the wall rows, one thread per wall and column c: density and psi of the boundary row r1 and the
+// second row r2 at c into the scratch field (read by the ghost rows' adjoint), and the ghost row beside the wall:
+// density (clamped), psi, and whether the clamp was active (derivative 0). The boundary row's densities at c - 1 and
+// c + 1 are summed again here from the populations, in the same order, rather than read from other threads.
 template <class T>
-__global__ __launch_bounds__(AB) void ka_prep_rows(const InstDesc* __restrict__ descs, int inst,
-                                                   const T* __restrict__ f, AdjScratch sc) {
-  const InstDesc& d = descs[inst];
-  const int nx = d.nx, ny = d.ny;
-  const int t = (int)(blockIdx.x * AB + threadIdx.x);
-  if (t >= 4 * nx) return;
-  const int j = t / nx, x = t % nx;
-  const int y = j == 0 ? 1 : (j == 1 ? 2 : (j == 2 ? ny - 3 : ny - 2));
-  if (y < 1 || y > ny - 2) return;
-  prep_node(d, f, (int64_t)nx * (ny - 2), nx, x, y, sc);
-}
-
-// forward ghost rows: density (clamped), psi, and whether the clamp was active (derivative 0)
-__global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ descs, int inst, AdjScratch sc) {
+__global__ __launch_bounds__(AB) void ka_wall_fwd(const InstDesc* __restrict__ descs, int inst,
+                                                  const T* __restrict__ f, AdjScratch sc) {
   const InstDesc& d = descs[inst];
   const int nx = d.nx, ny = d.ny;
   const int t = (int)(blockIdx.x * AB + threadIdx.x);
   if (t >= 2 * nx) return;
   const int wall = t / nx, c = t % nx;
+  const int64_t n = (int64_t)nx * (ny - 2);
   Field R{sc.rho, d.pitch}, P{sc.psi, d.pitch};
-  const int g = wall == 0 ? 0 : ny - 1, r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;
+  const int g = wall == 0 ? 0 : ny - 1, r1 = wall == 0 ? 1 : ny - 2, r2 = wall == 0 ? 2 : ny - 3;  // ny >= 4
+  const double rho1 = node_rho(f, n, nx, c, r1), rho2 = node_rho(f, n, nx, c, r2);
+  double dps;
+  R.at(c, r1) = rho1;
+  psi_dpsi(d, rho1, P.at(c, r1), dps);
+  R.at(c, r2) = rho2;
+  psi_dpsi(d, rho2, P.at(c, r2), dps);
   if (d.wall_mc) {  // solid wall rows (Eq. 14): psi = 0 there, no dependence on the state
     R.at(c, g) = 0.0;
     P.at(c, g) = 0.0;
@@ -159,8 +146,9 @@ __global__ __launch_bounds__(AB) void ka_ghost_fwd(const InstDesc* __restrict__ 
     return;
   }
   bool cl;
-  const double r0 = ghost_density(R.at(wrapx(c - 1, nx), r1), R.at(wrapx(c + 1, nx), r1), R.at(c, r1), R.at(c, r2),
-                                  d.cos_th[wall * nx + c], d.cot_th[wall * nx + c], d.wet_iters, d.rho_cap_hi, cl);
+  const double r0 = ghost_density(node_rho(f, n, nx, wrapx(c - 1, nx), r1), node_rho(f, n, nx, wrapx(c + 1, nx), r1),
+                                  rho1, rho2, d.cos_th[wall * nx + c], d.cot_th[wall * nx + c], d.wet_iters,
+                                  d.rho_cap_hi, cl);
   R.at(c, g) = r0;
   bool dm;
   P.at(c, g) = psi_f64(d, r0, dm);
@@ -732,9 +720,7 @@ hipError_t launch_adjoint_t(const InstDesc* d_desc, const InstDesc& h, int inst,
   const unsigned gfused = (unsigned)std::min((ntasks + 7) / 8 * 8, kAdjBlocks);  // a multiple of 8
   const bool walls = h.periodic_y == 0;  // periodic rows have no ghost rows and no wetting
   if (walls) {
-    hipLaunchKernelGGL(ka_prep_rows<T>, dim3((unsigned)((4 * h.nx + AB - 1) / AB)), dim3(AB), 0, s, d_desc, inst, f_n,
-                       sc);
-    hipLaunchKernelGGL(ka_ghost_fwd, dim3(gghost), dim3(AB), 0, s, d_desc, inst, sc);
+    hipLaunchKernelGGL(ka_wall_fwd<T>, dim3(gghost), dim3(AB), 0, s, d_desc, inst, f_n, sc);
   }
   if (ext)
     hipLaunchKernelGGL((ka_fused<true, T>), dim3(gfused), dim3(FL), 0, s, d_desc, inst, f_n, lam_np1, lam_n, sc, bw, ncb,
