@@ -506,8 +506,8 @@ def main():
         traffic_summary(args.traffic_summary)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the method on a single MI355X "
-              f"(asked for --gpus {args.gpus}).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs each lattice on a single MI355X, with no "
+              f"collectives (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
     import torch
