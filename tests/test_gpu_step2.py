@@ -104,8 +104,9 @@ def test_checked_two_step_launches_count_the_clamps(precision, check_every, step
     """Checked two-step launches count what checked one-step launches count. A droplet started above the largest
     density with real psi (0.5 against 0.458 at 0.85 T_c) makes psi clamp in the fluid and the ghost densities clamp
     at the walls for the first steps; checks every 2 steps (each the second step of a two-step launch) and every 5
-    (odd positions: one-step and two-step checks alternate) give the same checks, psi clamps, ghost-row clamps and
-    non-finite counts as one-step launches, the mass up to the order of its sums, the state bit for bit."""
+    (an odd period: checked one-step launches, the final check inside a two-step launch) give the same checks, psi
+    clamps, ghost-row clamps and non-finite counts as one-step launches, the mass up to the order of its sums, the
+    state bit for bit."""
     nx, ny = 96, 40
     th = np.radians(np.linspace(40.0, 140.0, nx))
     case = W.Case("s2_clamp", nx, ny, 0.85, th, th[::-1].copy(), [48.0], [0.5], [14.0], 0)
@@ -159,6 +160,46 @@ def test_batched_two_step_equals_single_contexts():
         assert np.array_equal(batch.populations(inst=i), single.populations()), i
         single.close()
     batch.close()
+
+
+@pytest.mark.parametrize("check_every", [2, 5])
+def test_batched_checked_two_step_launches_per_instance(check_every):
+    """Checks inside two-step launches of a batch: the k_finalize_diag fold over each instance's range of the
+    two-step task table gives every instance the checks, clamp counts and mass (up to the order of its sums) of the
+    same instance stepped alone with one-step launches (with a period of 2 every check is inside a two-step launch;
+    with 5, only the final one). Two of the five instances start above the largest density with real psi, so
+    their psi and ghost-row clamp counts are not zero."""
+    import paper_1501_05430_amd as P
+    rng = np.random.default_rng(11)
+    cases, rho_l = [], []
+    for k, (nx, ny) in enumerate([(64, 32), (97, 21), (150, 40), (33, 9), (128, 64)]):
+        th = np.radians(np.linspace(rng.uniform(30, 60), rng.uniform(120, 150), nx))
+        T = 0.85 if k in (1, 2) else rng.uniform(0.6, 0.9)
+        cases.append(W.Case(f"bc{k}", nx, ny, T, th, th[::-1].copy(), [nx / 2], [0.5], [0.35 * ny], 0))
+        rho_l.append(0.5 if k in (1, 2) else 0.0)
+    params = [P.make_params(c.nx, c.ny, c.T_over_Tc, precision="f32_shifted", step_variant=9, strip_rows=5,
+                            check_every=check_every, **P.fp32_options(c.T_over_Tc, "f32_shifted")) for c in cases]
+    batch = P.LBM(params)
+    for i, c in enumerate(cases):
+        batch.apply_wetting(c.theta_bottom, c.theta_top, inst=i)
+        batch.init_droplet(c.xc, c.yc, c.R, inst=i, rho_l=rho_l[i])
+    batch.step(23, inst=-1)
+    clamps = [0, 0]
+    for i, c in enumerate(cases):
+        single = gpu_sim(c, precision="f32_shifted", step_variant=5, check_every=check_every, init=False)
+        single.init_droplet(c.xc, c.yc, c.R, rho_l=rho_l[i])
+        single.step(23)
+        d1, d2 = single.diag(), batch.diag(inst=i)
+        assert np.array_equal(batch.populations(inst=i), single.populations()), i
+        for k in ("checks", "psi_clamps", "ghost_clamps", "nonfinite"):
+            assert d2[k] == d1[k], (i, k, d1, d2)
+        assert d2["mass"] == pytest.approx(d1["mass"], rel=1e-12), i
+        if rho_l[i] > 0:
+            clamps[0] += d1["psi_clamps"]
+            clamps[1] += d1["ghost_clamps"]
+        single.close()
+    batch.close()
+    assert clamps[0] > 0 and clamps[1] > 0, clamps
 
 
 def test_selection_outside_the_two_step_form_steps_one_at_a_time():
