@@ -103,7 +103,8 @@ typedef struct {
                              loads in flight; 9..12 the two-step kernel (two time steps per launch, geometric or
                              Martys-Chen walls, any collision and precision; periodic rows step one at a time) with
                              1, 2, 4 or 8 wavefronts per block; 0 = library default (two-step where it applies on
-                             contexts of at least 200 000 fluid nodes, one-step below).
+                             contexts of at least 50 000 fluid nodes, one-step below; one wavefront per two-step
+                             block while every instance has fewer than 3 000 000 fluid nodes).
                              Instance 0's value applies to the whole context (lbm_autotune may change it). Results
                              do not depend on it (bitwise). */
   int32_t boundary;       /* lbm_boundary [LBM_WALLS_Y] */

@@ -239,11 +239,17 @@ constexpr int kMinStripRows2 = 8, kMaxStripRows2 = 256;  // bounds of the defaul
 // several rounds of 24-row strips than with one round of taller ones (4096 x 2048: 45.7 against 34.0 GLUPS); FP32
 // loses a quarter of its rate to a partial second round, so it keeps the one-round rule.
 constexpr int kMaxStripRows2F64 = 24;
-// Below about 2e5 fluid nodes per context the two-step kernel has too few tasks to pay for its halo: one-step
-// launches are as fast or faster (200 x 100: 1.8 against 1.2 GLUPS; 512 x 256: 10.4 against 10.0 in FP32, 9.3
-// against 9.8 in FP64), above it two steps per launch win (724 x 362: 18.6 against 16.0, FP64 17.8 against 13.6;
-// 1024 x 512: 34.9 against 30.1, FP64 27.7 against 21.9; 4096 x 2048: 106.6 against 65, FP64 56.0 against 34.9).
-constexpr double kStep2MinNodes = 200000.0;
+// Below about 5e4 fluid nodes per context the two-step kernel has too few tasks to pay for its halo: one-step
+// launches are as fast (256 x 128: 2.90 against 2.86 GLUPS in FP32; FP64 2.73 against 3.00), above it two steps per
+// launch in one-wavefront blocks win (362 x 181: 5.67 against 5.59, FP64 5.93 against 5.11; 600 x 300: 14.7
+// against 11.4, FP64 14.8 against 10.9; 4096 x 2048 in its own shape: 109.5 against 65, FP64 57.0 against 34.9).
+constexpr double kStep2MinNodes = 50000.0;
+// Largest instance below this many fluid nodes: one wavefront per two-step block (56-column tiles; more, smaller
+// tasks balance better and need no barrier between wavefronts). 724 x 362: 21.0 against 18.9 GLUPS with four
+// (FP64 20.8 against 18.0); 2048 x 1024: 90.2 against 87.2 (FP64 54.3 against 52.3, the mixed form 74.8 against
+// 73.0, the paper's setting 67.9 against 66.4). Above it the halo lanes of narrow tiles cost more: 2896 x 1448
+// FP64 49.4 against 54.9, FP32 100.6 against 103.0; 4096 x 2048 FP64 52.6 against 57.6.
+constexpr double kNarrow2MaxNodes = 3.0e6;
 constexpr int kStep2Halo = 8;  // lanes beyond a two-step tile's outputs (three of step A and one of psi per side)
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr int kMaxDrops = 4096;
@@ -617,18 +623,22 @@ int lbm_create(const lbm_params* p, int32_t n_inst, void* d_workspace, size_t ws
     c->prefetch = kDefaultPrefetch64;
   }
   // two steps per launch by default (where the selection allows it) on contexts of at least kStep2MinNodes fluid
-  // nodes; variants 1..8 choose a one-step shape, 9..12 the two-step kernel with 1, 2, 4 or 8 wavefronts per block
+  // nodes, in blocks of one wavefront while every instance is below kNarrow2MaxNodes; variants 1..8 choose a
+  // one-step shape, 9..12 the two-step kernel with 1, 2, 4 or 8 wavefronts per block
   {
     double nodes = 0;
     for (int i = 0; i < n_inst; ++i) nodes += (double)p[i].nx * (p[i].ny - 2);
     c->step2 = nodes >= kStep2MinNodes;
     int min_nx = p[0].nx;
+    double max_inst = 0;
     bool special = true;  // every instance takes the tau = 1 BGK specialisation (see tau1)
     for (int i = 0; i < n_inst; ++i) {
       min_nx = std::min(min_nx, p[i].nx);
+      max_inst = std::max(max_inst, (double)p[i].nx * (p[i].ny - 2));
       special = special && p[i].tau == 1.0 && !uses_mrt(p[i]) && p[i].boundary == LBM_WALLS_Y;
     }
-    if (c->storage == STORE_F32 && special && nodes >= kWide2MinNodes && min_nx >= kWide2MinNx) c->waves2 = 8;
+    if (max_inst < kNarrow2MaxNodes) c->waves2 = 1;
+    else if (c->storage == STORE_F32 && special && nodes >= kWide2MinNodes && min_nx >= kWide2MinNx) c->waves2 = 8;
   }
   if (p[0].step_variant > 0 && p[0].step_variant <= 2 * kNumWaveChoices) {
     c->waves = kWaveChoices[(p[0].step_variant - 1) % kNumWaveChoices];
