@@ -31,6 +31,8 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
               for n in ("lbm_step2.hip", "lbm_device.h", "lbm_internal.h")]
 ADJOINT_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
                for n in ("lbm_adjoint.hip", "lbm_device.h", "lbm_internal.h")]
+STEP1_SRC = [os.path.join(ROOT, "paper_1501_05430_amd", "csrc", n)
+             for n in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step2_f32_c3.json")
 TRAFFIC_FILE_C4 = os.path.join(ROOT, "profiles", "traffic_step2_f32_batched_c4.json")
 TRAFFIC_FILE_MIXED = os.path.join(ROOT, "profiles", "traffic_step2_mixed_c3.json")
@@ -66,6 +68,12 @@ TRAFFIC_SPECS = {
         match="k_step2<float, 4, false, true, false>", workload="c3", args="--paper-setting-only --steps 20",
         desc="k_step2<float, W=4, general collision> in the paper's setting (piecewise-linear EOS at a density ratio "
              "of 1000, kappa = 0.5, MRT with diag(0,1,...,1)), same lattice, FP32 shifted by rho_v"),
+    "step_f32_c3": dict(
+        match="k_step<float, false, true, 8, true, ", workload="c3", steps=1, sources="step",
+        args="--steps 20 --warmup 5 --no-extras --no-cpu-baseline --step-variant 8",
+        desc="k_step<float, TAU1=true, W=8, PF=true> (one time step per launch, consecutive launches walking the row "
+             "strips in alternate directions; FP32 storage shifted by rho_v), 4096x2048 lattice, the headline's "
+             "workload with step_variant 8"),
     "adjoint_f64_c3": dict(
         match="ka_fused<false, double>", workload="c3", run="adjoint_c3", args="--adjoint-only", steps=1,
         bytes_per_update=216, state_elem=8, sources="adjoint",
@@ -90,7 +98,7 @@ def traffic_summary(name):
     from paper_1501_05430_amd import workloads as W
     spec = TRAFFIC_SPECS[name]
     run = spec.get("run", name)
-    sources = ADJOINT_SRC if spec.get("sources") == "adjoint" else KERNEL_SRC
+    sources = {"adjoint": ADJOINT_SRC, "step": STEP1_SRC}.get(spec.get("sources"), KERNEL_SRC)
     steps = spec.get("steps", 2)
     runs = {}
     for counter, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
@@ -496,6 +504,9 @@ def main():
                     help="only the paper's setting on the headline lattice (piecewise EOS, kappa = 0.5, MRT), --steps")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint legs on the headline lattice and print their JSON (for profiling)")
+    ap.add_argument("--step-variant", type=int, default=0,
+                    help="force the headline's step shape (lbm_params.step_variant: 1..8 one-step kernel, 9..12 "
+                         "two-step; 0 = library default), to profile a kernel the default does not run")
     ap.add_argument("--precision", default="f32_shifted", choices=["f32_shifted", "f32_shifted_mixed", "f64"],
                     help="the timed form: FP32 arithmetic (default), the mixed form (FP64 force and equilibrium) "
                          "or FP64")
@@ -531,7 +542,8 @@ def main():
 
     case = W.c3_large()
     ceilings = bandwidth_ceilings(case.nx, case.ny)
-    sim = make_sim(case, args.precision, check_every=100)
+    sim = make_sim(case, args.precision, check_every=100,
+                   **({"step_variant": args.step_variant} if args.step_variant else {}))
     if args.autotune:
         sim.autotune(trial_steps=10)
     sim.step(args.warmup)
@@ -552,6 +564,8 @@ def main():
         bytes_alg = 144 * nodes  # 9 FP64 populations read + 9 written per fluid node and step
         achieved = bytes_alg / (ms_step * 1e-3) / 1e9
     traffic, per_launch = profile_traffic(TRAFFIC_FILE_F64 if f64 else (TRAFFIC_FILE_MIXED if mixed else TRAFFIC_FILE))
+    if args.step_variant:  # a forced shape: the committed counters are the default kernel's
+        traffic, per_launch = None, 1
 
     out = {
         "metric": "MLUPS & % HBM roofline; FP32/batched/adjoint vs plain FP64 at stated error",
@@ -580,8 +594,10 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             # the dominant kernel: two time steps per launch; traffic is its HBM bytes per launch (counters, when
             # current), traffic_gbs those bytes over this run's time per launch
-            "kernel": f"k_step2<{'double' if f64 else 'float'}, {waves2}, {'true' if mixed else 'false'}, false, false> "
-                      "(two time steps per launch; one launch in 50 its checked instance)", "steps_per_launch": 2,
+            "kernel": (f"the shape step_variant {args.step_variant} selects" if args.step_variant else
+                       f"k_step2<{'double' if f64 else 'float'}, {waves2}, {'true' if mixed else 'false'}, false, "
+                       "false> (two time steps per launch; one launch in 50 its checked instance)"),
+            "steps_per_launch": 1 if 0 < args.step_variant <= 8 else 2,
             "traffic_gbs": round(traffic / (per_launch * ms_step * 1e-3) / 1e9, 1) if traffic else None,
             # plain memory movement on this GPU (bw_probe.hip): float4 / float ping-pong copies of the state's size
             # and the step's access pattern without arithmetic

@@ -16,7 +16,7 @@ def test_traffic_summary_is_current_and_consistent(name):
     path = os.path.join(bench.ROOT, "profiles", f"traffic_{name}.json")
     with open(path) as f:
         tr = json.load(f)
-    sources = bench.ADJOINT_SRC if spec.get("sources") == "adjoint" else bench.KERNEL_SRC
+    sources = {"adjoint": bench.ADJOINT_SRC, "step": bench.STEP1_SRC}.get(spec.get("sources"), bench.KERNEL_SRC)
     assert tr["kernel_source_sha256"] == bench.kernel_sha(sources), "kernel changed since its counters were taken"
     assert bench.profile_traffic(path, sources)[0] == tr["hbm_bytes_per_launch"]
     kib = tr["kernel_counters_kib_per_launch"]
